@@ -1,0 +1,183 @@
+/*
+ * scf.h -- C ABI of libscf, the MI355X (gfx950) implementation of the
+ * basis-expansion ("self-consistent field", SCF) N-body hot path.
+ *
+ * The method (Sec. 2, Eqs. total_potential, psi_nlm, a_nlm, sumanlm): the
+ * cluster potential is expanded in bi-orthogonal basis pairs
+ *     psi(x) = sum_{n,l,m} a_nlm U_n^l(r) Y_l^m(theta, phi)
+ * whose coefficients are estimated from the N particles as
+ *     a_nlm = -sum_k m_k U_n^l(r_k) conj(Y_l^m(theta_k, phi_k)).
+ * The radial functions are the Zhao (1996) family whose zeroth mode is
+ * Eq. (u00), U_0^0 ~ (1 + (r/b)^(1/alpha))^(-alpha):
+ *     U_n^l(r) = -s^l (1 + s^(1/alpha))^(-alpha(2l+1)) C_n^(lambda_l)(xi) / sqrt(N_nl),
+ *     s = r/b, xi = (s^(1/alpha)-1)/(s^(1/alpha)+1), lambda_l = (2l+1)alpha + 1/2,
+ * normalised so that -int rho_nlm psi*_n'l'm' = delta (energy inner product
+ * N_nl = (b/4 pi G) int [s^2 f'^2 + l(l+1) f^2] ds).  alpha = 1 is the
+ * Hernquist-Ostriker basis, alpha = 1/2 the Clutton-Brock basis; any
+ * 0 < alpha <= 1 is accepted.  Y_l^m are complex orthonormal harmonics with the
+ * Condon-Shortley phase.  Stars are integrated in the accelerating,
+ * non-rotating cluster frame of Sec. 2.1, centred on a test particle that
+ * orbits the analytic host potential of Appendix A:
+ *     a_i = -grad psi_SCF(x_i) - grad psi_host(R + x_i) + grad psi_host(R).
+ *
+ * CONVENTIONS
+ *  - Particle arrays are structure-of-arrays, one contiguous device array per
+ *    component (x, y, z, vx, vy, vz, m, ax, ay, az), element type float for a
+ *    plan of dtype SCF_F32 and double for SCF_F64.
+ *  - Coefficients are always double, n-major:
+ *        index(n, l, j) = n*(lmax+1)^2 + l*l + j,
+ *        j = 0 -> Re a_nl0;  j = 2m-1 -> Re a_nlm;  j = 2m -> Im a_nlm  (1<=m<=l),
+ *    a_{nl,-m} = (-1)^m conj(a_nlm) being implied.
+ *  - Device pointers are caller-owned (e.g. torch tensors).  The workspace is a
+ *    caller-allocated device buffer of at least the size returned by the
+ *    matching *_workspace_size query; the library allocates no device memory on
+ *    these calls.  Host structs and host arrays are read (and, where stated,
+ *    written) during the call only.
+ *  - stream is a hipStream_t (NULL = the null stream).  Calls enqueue work and
+ *    return; device outputs are valid once the stream reaches that point.
+ *    Host outputs (centre states, host gradients) are valid on return.
+ *  - Errors: arguments are validated before any launch; on error nothing is
+ *    enqueued and outputs are untouched.  HIP failures return SCF_ERR_HIP.
+ *    scf_last_error() gives a thread-local message for the last failure.
+ *    n == 0 is a valid, successful call.  No C++ exception crosses the ABI.
+ */
+#ifndef SCF_H
+#define SCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SCF_OK = 0,
+  SCF_ERR_INVALID_ARG = 1, /* null pointer, negative size, bad enum, bad offsets */
+  SCF_ERR_UNSUPPORTED = 2, /* (nmax, lmax) or alpha outside the compiled range */
+  SCF_ERR_WORKSPACE = 3,   /* workspace pointer null or smaller than required */
+  SCF_ERR_NONFINITE = 4,   /* reserved: non-finite input detected */
+  SCF_ERR_HIP = 5          /* a HIP runtime call failed (message in scf_last_error) */
+} scf_status;
+
+typedef enum { SCF_F32 = 0, SCF_F64 = 1 } scf_dtype;
+
+/* Basis (Sec. 2): n = 0..nmax, l = 0..lmax inclusive; scale radius b > 0,
+ * exponent 0 < alpha <= 1, gravitational constant G > 0. */
+typedef struct {
+  int32_t nmax, lmax;
+  double alpha, b, G;
+} scf_basis;
+
+/* Host-potential components (Appendix A; LOG and PLUMMER are the textbook
+ * forms).  Parameters p[]:
+ *   SCF_HOST_LOG        psi = (v0^2/2) ln(r^2 + rc^2)            p = {v0, rc}
+ *   SCF_HOST_HERNQUIST  psi = -G M / (r + a)                       p = {M, a}
+ *   SCF_HOST_NFW        psi = -G M ln(1 + r/rs) / r                p = {M, rs}
+ *   SCF_HOST_MN         psi = -G M / sqrt(R^2 + (a + sqrt(z^2+b^2))^2)  p = {M, a, b}
+ *   SCF_HOST_PLUMMER    psi = -G M / sqrt(r^2 + a^2)               p = {M, a}   */
+enum {
+  SCF_HOST_LOG = 1,
+  SCF_HOST_HERNQUIST = 2,
+  SCF_HOST_NFW = 3,
+  SCF_HOST_MN = 4,
+  SCF_HOST_PLUMMER = 5
+};
+#define SCF_MAX_HOST_COMP 8
+
+typedef struct {
+  int32_t kind, pad;
+  double p[3];
+} scf_host_comp;
+
+typedef struct {
+  int32_t ncomp, pad; /* 0 <= ncomp <= SCF_MAX_HOST_COMP; 0 = isolated cluster */
+  double G;
+  scf_host_comp comp[SCF_MAX_HOST_COMP];
+} scf_host;
+
+typedef struct scf_plan scf_plan;
+
+/* scf_step flags */
+#define SCF_STEP_ACC_VALID 1u /* ax, ay, az already hold a(x) at entry */
+
+/* (nmax+1)(lmax+1)^2, or 0 for negative arguments. */
+int64_t scf_ncoef(int32_t nmax, int32_t lmax);
+
+/* Create a plan for one basis and dtype on the current HIP device: basis
+ * tables (normalisations of Sec. 2, recurrence constants) are computed in
+ * double precision on the host and copied to the device.  flags must be 0. */
+scf_status scf_plan_create(scf_plan** plan, const scf_basis* basis, int32_t dtype, uint32_t flags);
+void scf_plan_destroy(scf_plan* plan);
+
+/* Workspace bytes for scf_coeffs / scf_forces / scf_step on n particles
+ * (nclusters = 1) or for scf_step_batched with nclusters clusters totalling n. */
+scf_status scf_workspace_size(const scf_plan* plan, int64_t n, int32_t nclusters, size_t* bytes);
+
+/* Coefficients of Eq. (sumanlm): coef (device, ncoef doubles) receives
+ * a_nlm = -sum_k m_k U_nl(r_k) conj(Y_lm), about the origin of x, y, z.
+ * The particle sum is accumulated in the plan's dtype over bounded runs of
+ * particles and combined across thread blocks in double precision. */
+scf_status scf_coeffs(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
+                      const void* m, double* coef, void* ws, size_t ws_bytes, void* stream);
+
+/* Accelerations at n points from coefficients coef (device, ncoef doubles):
+ * a = -grad psi_SCF (Eq. total_potential) plus, if host != NULL and
+ * host->ncomp > 0, the tidal term -grad psi_host(centre + x) + grad psi_host(centre)
+ * with centre[3] a host array.  pot (nullable) receives psi_SCF. */
+scf_status scf_forces(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
+                      const double* coef, const scf_host* host, const double* centre, void* ax,
+                      void* ay, void* az, void* pot, void* ws, size_t ws_bytes, void* stream);
+
+/* nsteps kick-drift-kick leapfrog steps of size dt in the cluster frame:
+ * every step recomputes the coefficients from all particles (Eq. sumanlm),
+ * the SCF + tidal accelerations, and kicks/drifts the particles.  The frame
+ * centre (centre[6] = R, V, host array, in/out) follows the same leapfrog in
+ * the host potential alone, in double precision on the host.  The state
+ * (x, y, z, vx, vy, vz, and ax, ay, az = a at the final positions) is
+ * synchronised on return.  With SCF_STEP_ACC_VALID ax, ay, az must hold a(x)
+ * at entry; otherwise the call first evaluates it.  coef_last (device,
+ * nullable) receives the coefficients of the final positions. */
+scf_status scf_step(scf_plan* plan, int64_t n, void* x, void* y, void* z, void* vx, void* vy,
+                    void* vz, const void* m, void* ax, void* ay, void* az, uint32_t step_flags,
+                    const scf_host* host, double* centre, double dt, int32_t nsteps,
+                    double* coef_last, void* ws, size_t ws_bytes, void* stream);
+
+/* scf_step for nclusters independent clusters concatenated in the particle
+ * arrays: cluster c owns particles [offsets[c], offsets[c+1]) (host array,
+ * offsets[0] = 0, non-decreasing).  Each cluster has its own coefficients and
+ * frame centre (centres: host, nclusters*6, in/out); all share the host
+ * potential.  The step's kernels are launched once for all clusters through
+ * a static work list, captured in a HIP graph and replayed every step.
+ * coef_last (device, nullable) receives nclusters*ncoef doubles. */
+scf_status scf_step_batched(scf_plan* plan, int32_t nclusters, const int64_t* offsets, void* x,
+                            void* y, void* z, void* vx, void* vy, void* vz, const void* m,
+                            void* ax, void* ay, void* az, uint32_t step_flags, const scf_host* host,
+                            double* centres, double dt, int32_t nsteps, double* coef_last,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Reverse mode of scf_step over one segment of nsteps steps starting from
+ * the synchronised state (x0..vz0, centre0[6], host array).  The forward
+ * segment is recomputed on the device from that state.  lam[6] are device
+ * arrays (x, y, z, vx, vy, vz components) holding dL/d(final state) on entry
+ * and dL/d(initial state) on return; lam_centre[6] (host, in/out) likewise
+ * for the centre R, V; grad_host (host, host->ncomp*3 doubles) accumulates
+ * dL/d(host parameters p[]).  Blocks until the results are on the host. */
+scf_status scf_step_adjoint(scf_plan* plan, int64_t n, const void* x0, const void* y0,
+                            const void* z0, const void* vx0, const void* vy0, const void* vz0,
+                            const void* m, const scf_host* host, const double* centre0, double dt,
+                            int32_t nsteps, void* const* lam, double* lam_centre,
+                            double* grad_host, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for scf_step_adjoint (grows with n * nsteps: the segment's
+ * positions are kept on the device). */
+scf_status scf_adjoint_workspace_size(const scf_plan* plan, int64_t n, int32_t nsteps,
+                                      size_t* bytes);
+
+const char* scf_status_string(scf_status status);
+const char* scf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCF_H */

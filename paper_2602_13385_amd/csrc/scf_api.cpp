@@ -1,0 +1,653 @@
+// libscf C ABI: plan management, basis tables, argument validation, the
+// double-precision centre orbit (Sec. 2.1) and the launch sequences of the
+// hot path.  Declared in include/scf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/scf.h"
+#include "host_field.h"
+#include "scf_internal.h"
+
+using namespace scf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+scf_status fail(scf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(SCF_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                  __FILE__, __LINE__);                                                    \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// basis tables (double precision, host)
+// ---------------------------------------------------------------------------
+// Monic Gegenbauer recurrence p_n = xi p_{n-1} - beta_n p_{n-2}:
+// from n C_n = 2(n+lambda-1) xi C_{n-1} - (n+2 lambda-2) C_{n-2} and the
+// leading coefficient k_n = 2^n (lambda)_n / n!.
+double gegen_beta(int n, double lam) {
+  if (n < 2) return 0.0;
+  return (n + 2.0 * lam - 2.0) * (n - 1.0) / (4.0 * (n + lam - 1.0) * (n + lam - 2.0));
+}
+double gegen_lead(int n, double lam) {
+  return std::exp(n * std::log(2.0) + std::lgamma(lam + n) - std::lgamma(lam) - std::lgamma(n + 1.0));
+}
+// Monic-scaled associated Legendre recurrence Qt_l = c Qt_{l-1} - gamma Qt_{l-2}
+double legendre_gamma(int l, int m) {
+  if (l < m + 2) return 0.0;
+  return (l + m - 1.0) * (l - m - 1.0) / ((2.0 * l - 1.0) * (2.0 * l - 3.0));
+}
+// rho_lm = d^m P_l / dx^m  /  Qt_l^m
+double legendre_rho(int l, int m) {
+  double r = 1.0;
+  for (int k = 2 * m - 1; k > 1; k -= 2) r *= k;  // (2m-1)!!
+  for (int ll = m + 1; ll <= l; ++ll) r *= (2.0 * ll - 1.0) / (ll - m);
+  return r;
+}
+double ylm_norm(int l, int m) {
+  double lg = std::lgamma(l - m + 1.0) - std::lgamma(l + m + 1.0);
+  return std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * std::exp(lg));
+}
+
+// f_nl(s) = -s^l q^(-alpha(2l+1)) C_n^(lambda)(xi) and its s-derivative,
+// evaluated with the monic recurrence and its derivative.
+void radial_f(double alpha, int l, int n, double s, double& f, double& df) {
+  const double lam = (2.0 * l + 1.0) * alpha + 0.5;
+  const double t = std::pow(s, 1.0 / alpha);
+  const double q = 1.0 + t;
+  const double xi = 1.0 - 2.0 / q;
+  const double dt = (1.0 / alpha) * std::pow(s, 1.0 / alpha - 1.0);  // dt/ds
+  const double dxi = 2.0 * dt / (q * q);
+  double p0 = 1.0, p1 = xi, d0 = 0.0, d1 = 1.0, p = 1.0, dp = 0.0;
+  if (n == 0) {
+    p = 1.0;
+    dp = 0.0;
+  } else if (n == 1) {
+    p = xi;
+    dp = 1.0;
+  } else {
+    for (int k = 2; k <= n; ++k) {
+      double b = gegen_beta(k, lam);
+      double p2 = xi * p1 - b * p0;
+      double d2 = p1 + xi * d1 - b * d0;
+      p0 = p1;
+      p1 = p2;
+      d0 = d1;
+      d1 = d2;
+    }
+    p = p1;
+    dp = d1;
+  }
+  const double kn = gegen_lead(n, lam);
+  const double pre = std::pow(s, double(l)) * std::pow(q, -alpha * (2.0 * l + 1.0));
+  // d pre / ds = pre * (l/s - alpha(2l+1) dt / q)
+  const double dpre = (l > 0 ? l * std::pow(s, l - 1.0) * std::pow(q, -alpha * (2.0 * l + 1.0)) : 0.0) -
+                      pre * alpha * (2.0 * l + 1.0) * dt / q;
+  f = -kn * pre * p;
+  df = -kn * (dpre * p + pre * dp * dxi);
+}
+
+// Energy-norm normalisation N_nl = (b / 4 pi G) int_0^inf [s^2 f'^2 + l(l+1) f^2] ds.
+// alpha = 1: closed form (Hernquist & Ostriker 1992).  Otherwise composite
+// 16-point Gauss-Legendre quadrature in v = ln s over [-60, 60].
+double norm_nl(double alpha, double b, double G, int n, int l) {
+  if (alpha == 1.0) {
+    const double K = 0.5 * n * (n + 4.0 * l + 3.0) + (l + 1.0) * (2.0 * l + 1.0);
+    const double lg = std::lgamma(n + 4.0 * l + 3.0) - std::lgamma(n + 1.0) - 2.0 * std::lgamma(2.0 * l + 1.5);
+    return b / G * K * std::exp(lg - (8.0 * l + 6.0) * std::log(2.0)) / (n + 2.0 * l + 1.5);
+  }
+  static double xs[16], ws[16];
+  static bool init = false;
+  if (!init) {
+    for (int i = 0; i < 16; ++i) {  // Newton iteration on P_16
+      double x = std::cos(M_PI * (i + 0.75) / 16.5);
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= 16; ++k) {
+          double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        double dp = 16.0 * (x * p1 - p0) / (x * x - 1.0);
+        double dx = p1 / dp;
+        x -= dx;
+        if (std::fabs(dx) < 1e-16) break;
+      }
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= 16; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = 16.0 * (x * p1 - p0) / (x * x - 1.0);
+      xs[i] = x;
+      ws[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    init = true;
+  }
+  const int panels = 960;
+  const double v0 = -60.0, v1 = 60.0, hw = (v1 - v0) / panels;
+  double acc = 0.0;
+  for (int pnl = 0; pnl < panels; ++pnl) {
+    const double c = v0 + (pnl + 0.5) * hw;
+    for (int i = 0; i < 16; ++i) {
+      const double v = c + 0.5 * hw * xs[i];
+      const double s = std::exp(v);
+      double f, df;
+      radial_f(alpha, l, n, s, f, df);
+      double val = (s * s * df * df + l * (l + 1.0) * f * f) * s;
+      if (std::isfinite(val)) acc += 0.5 * hw * ws[i] * val;
+    }
+  }
+  return b / (4.0 * M_PI * G) * acc;
+}
+
+}  // namespace
+
+struct scf_plan {
+  scf_basis basis;
+  int dtype;
+  int device;
+  int nmax, lmax, nmaxc;
+  int64_t T;
+  int amode;
+  Engine* eng;
+  size_t rs;  // sizeof real
+  void* d_beta_rad = nullptr;
+  void* d_beta_ang = nullptr;
+  double* d_cs = nullptr;
+  double* d_fw = nullptr;
+  std::vector<double> h_cs, h_fw;
+};
+
+namespace {
+
+int coef_blocks(const scf_plan* p, int64_t n, int64_t* chunk) {
+  if (n <= 0) {
+    *chunk = 0;
+    return 0;
+  }
+  const int P = p->eng->stage_particles();
+  const int64_t stages = (n + P - 1) / P;
+  const int64_t target = 2048;
+  const int64_t per = (stages + target - 1) / target;
+  *chunk = per * P;
+  return (int)((n + *chunk - 1) / *chunk);
+}
+
+constexpr int kReduceChunks = 16;
+
+struct WsLayout {
+  size_t partials, red1, coef, W, total;
+};
+
+WsLayout ws_layout(const scf_plan* p, int64_t n, int nclusters, int nblocks) {
+  WsLayout L;
+  size_t off = 0;
+  L.partials = off;
+  off += align256((size_t)std::max(nblocks, 1) * p->T * p->rs);
+  L.red1 = off;
+  off += align256((size_t)kReduceChunks * p->T * sizeof(double) * std::max(nclusters, 1));
+  L.coef = off;
+  off += align256((size_t)p->T * sizeof(double) * std::max(nclusters, 1));
+  L.W = off;
+  off += align256((size_t)(p->nmaxc + 1) * (p->lmax + 1) * (p->lmax + 1) * p->rs *
+                  std::max(nclusters, 1));
+  L.total = off;
+  (void)n;
+  return L;
+}
+
+template <typename R>
+void fill_host_params(HostParams<R>& hp, const scf_host* h) {
+  std::memset(&hp, 0, sizeof(hp));
+  if (!h) return;
+  hp.ncomp = h->ncomp;
+  hp.G = R(h->G);
+  for (int c = 0; c < h->ncomp; ++c) {
+    hp.kind[c] = h->comp[c].kind;
+    for (int k = 0; k < 3; ++k) hp.p[c][k] = R(h->comp[c].p[k]);
+  }
+}
+
+scf_status check_host(const scf_host* h) {
+  if (!h) return SCF_OK;
+  if (h->ncomp < 0 || h->ncomp > SCF_MAX_HOST_COMP)
+    return fail(SCF_ERR_INVALID_ARG, "host->ncomp = %d outside [0, %d]", h->ncomp, SCF_MAX_HOST_COMP);
+  if (h->ncomp > 0 && !(h->G > 0.0)) return fail(SCF_ERR_INVALID_ARG, "host->G must be > 0");
+  for (int c = 0; c < h->ncomp; ++c) {
+    const int k = h->comp[c].kind;
+    if (k < SCF_HOST_LOG || k > SCF_HOST_PLUMMER)
+      return fail(SCF_ERR_INVALID_ARG, "host component %d has unknown kind %d", c, k);
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(h->comp[c].p[q]))
+        return fail(SCF_ERR_INVALID_ARG, "host component %d parameter %d is not finite", c, q);
+    if (k != SCF_HOST_MN && !(h->comp[c].p[1] > 0.0))
+      return fail(SCF_ERR_INVALID_ARG, "host component %d: scale parameter must be > 0", c);
+  }
+  return SCF_OK;
+}
+
+// centre acceleration -grad psi_host(R) in double precision
+void centre_accel(const HostParams<double>& H, const double* R, double* g) {
+  double gx = 0, gy = 0, gz = 0;
+  if (H.ncomp > 0) host_grad<double>(H, R[0], R[1], R[2], gx, gy, gz);
+  g[0] = -gx;
+  g[1] = -gy;
+  g[2] = -gz;
+}
+
+template <typename R>
+void fill_force_common(ForceArgs<R>& fa, const scf_plan* p) {
+  std::memset(&fa, 0, sizeof(fa));
+  fa.beta_rad = (const R*)p->d_beta_rad;
+  fa.beta_ang = (const R*)p->d_beta_ang;
+  fa.binv = R(1.0 / p->basis.b);
+  fa.alpha = R(p->basis.alpha);
+  fa.inv_alpha = R(1.0 / p->basis.alpha);
+  fa.amode = p->amode;
+}
+
+template <typename R>
+void fill_coef_common(CoefArgs<R>& ca, const scf_plan* p) {
+  std::memset(&ca, 0, sizeof(ca));
+  ca.beta_rad = (const R*)p->d_beta_rad;
+  ca.beta_ang = (const R*)p->d_beta_ang;
+  ca.T = (int)p->T;
+  ca.nmax = p->nmax;
+  ca.binv = R(1.0 / p->basis.b);
+  ca.alpha = R(p->basis.alpha);
+  ca.inv_alpha = R(1.0 / p->basis.alpha);
+  ca.amode = p->amode;
+}
+
+// coefficients of n particles into coef (device) and force weights W (device)
+template <typename R>
+scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                      const void* m, double* coef, void* W, char* ws, const WsLayout& L, int nb,
+                      int64_t chunk, hipStream_t s) {
+  if (n == 0) {
+    // empty particle set: all coefficients vanish
+    if (coef) HIP_TRY(launch_fill(coef, p->T, 0.0, s));
+    HIP_TRY(launch_make_w(p->dtype, coef ? coef : (double*)(ws + L.coef), (int)p->T, p->nmax,
+                          p->lmax, p->nmaxc, p->d_fw, W, s));
+    return SCF_OK;
+  }
+  CoefArgs<R> ca;
+  fill_coef_common(ca, p);
+  ca.x = (const R*)x;
+  ca.y = (const R*)y;
+  ca.z = (const R*)z;
+  ca.m = (const R*)m;
+  ca.begin = 0;
+  ca.chunk = chunk;
+  ca.n = n;
+  ca.partials = (R*)(ws + L.partials);
+  HIP_TRY(p->eng->launch_coef(&ca, nb, s));
+  double* red1 = (double*)(ws + L.red1);
+  const int nch = std::min(kReduceChunks, nb);
+  HIP_TRY(launch_reduce(p->dtype, ca.partials, nb, (int)p->T, nch, red1, s));
+  HIP_TRY(launch_finalize(p->dtype, red1, nch, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
+                          p->d_fw, coef, W, s));
+  return SCF_OK;
+}
+
+template <typename R>
+scf_status run_field(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx, void* vy,
+                     void* vz, void* ax, void* ay, void* az, void* pot, const void* W,
+                     const HostParams<R>& hp, const double* cen, int mode, double kick,
+                     double drift, hipStream_t s) {
+  if (n == 0) return SCF_OK;
+  ForceArgs<R> fa;
+  fill_force_common(fa, p);
+  fa.x = (R*)x;
+  fa.y = (R*)y;
+  fa.z = (R*)z;
+  fa.vx = (R*)vx;
+  fa.vy = (R*)vy;
+  fa.vz = (R*)vz;
+  fa.ax = (R*)ax;
+  fa.ay = (R*)ay;
+  fa.az = (R*)az;
+  fa.pot = (R*)pot;
+  fa.W = (const R*)W;
+  fa.n = n;
+  fa.kick = R(kick);
+  fa.drift = R(drift);
+  fa.host = hp;
+  fa.cx = R(cen ? cen[0] : 0.0);
+  fa.cy = R(cen ? cen[1] : 0.0);
+  fa.cz = R(cen ? cen[2] : 0.0);
+  fa.gcx = R(cen ? cen[3] : 0.0);
+  fa.gcy = R(cen ? cen[4] : 0.0);
+  fa.gcz = R(cen ? cen[5] : 0.0);
+  HIP_TRY(p->eng->launch_force(&fa, (n + 255) / 256, mode, s));
+  return SCF_OK;
+}
+
+bool ptr_ok(const void* q) { return q != nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t scf_ncoef(int32_t nmax, int32_t lmax) {
+  if (nmax < 0 || lmax < 0) return 0;
+  return (int64_t)(nmax + 1) * (lmax + 1) * (lmax + 1);
+}
+
+const char* scf_status_string(scf_status st) {
+  switch (st) {
+    case SCF_OK: return "SCF_OK";
+    case SCF_ERR_INVALID_ARG: return "SCF_ERR_INVALID_ARG";
+    case SCF_ERR_UNSUPPORTED: return "SCF_ERR_UNSUPPORTED";
+    case SCF_ERR_WORKSPACE: return "SCF_ERR_WORKSPACE";
+    case SCF_ERR_NONFINITE: return "SCF_ERR_NONFINITE";
+    case SCF_ERR_HIP: return "SCF_ERR_HIP";
+  }
+  return "unknown scf_status";
+}
+
+const char* scf_last_error(void) { return g_last_error.c_str(); }
+
+scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype, uint32_t flags) {
+  if (!out || !basis) return fail(SCF_ERR_INVALID_ARG, "plan and basis must be non-null");
+  *out = nullptr;
+  if (flags != 0) return fail(SCF_ERR_INVALID_ARG, "flags must be 0");
+  if (dtype != SCF_F32 && dtype != SCF_F64) return fail(SCF_ERR_INVALID_ARG, "bad dtype %d", dtype);
+  if (basis->nmax < 0 || basis->lmax < 0)
+    return fail(SCF_ERR_INVALID_ARG, "nmax and lmax must be >= 0");
+  if (!(basis->alpha > 0.0 && basis->alpha <= 1.0))
+    return fail(SCF_ERR_UNSUPPORTED, "alpha = %g outside (0, 1]", basis->alpha);
+  if (!(basis->b > 0.0) || !std::isfinite(basis->b)) return fail(SCF_ERR_INVALID_ARG, "b must be > 0");
+  if (!(basis->G > 0.0) || !std::isfinite(basis->G)) return fail(SCF_ERR_INVALID_ARG, "G must be > 0");
+  Engine* eng = find_engine(dtype, basis->nmax, basis->lmax);
+  if (!eng)
+    return fail(SCF_ERR_UNSUPPORTED, "no kernel for nmax = %d, lmax = %d", basis->nmax, basis->lmax);
+  scf_plan* p = new scf_plan();
+  p->basis = *basis;
+  p->dtype = dtype;
+  HIP_TRY(hipGetDevice(&p->device));
+  p->nmax = basis->nmax;
+  p->lmax = basis->lmax;
+  p->nmaxc = eng->nmaxc();
+  p->T = scf_ncoef(basis->nmax, basis->lmax);
+  p->amode = basis->alpha == 1.0 ? 0 : (basis->alpha == 0.5 ? 1 : 2);
+  p->eng = eng;
+  p->rs = eng->real_size();
+  const int L1 = p->lmax + 1, NW = p->nmaxc + 1;
+  std::vector<double> brad((size_t)L1 * NW, 0.0), bang((size_t)L1 * L1, 0.0);
+  for (int l = 0; l <= p->lmax; ++l) {
+    const double lam = (2.0 * l + 1.0) * basis->alpha + 0.5;
+    for (int n = 0; n <= p->nmaxc; ++n) brad[(size_t)l * NW + n] = gegen_beta(n, lam);
+  }
+  for (int m = 0; m <= p->lmax; ++m)
+    for (int l = 0; l <= p->lmax; ++l) bang[(size_t)m * L1 + l] = legendre_gamma(l, m);
+  const int L2 = L1 * L1;
+  p->h_cs.assign(p->T, 0.0);
+  p->h_fw.assign(p->T, 0.0);
+  for (int n = 0; n <= p->nmax; ++n) {
+    for (int l = 0; l <= p->lmax; ++l) {
+      const double lam = (2.0 * l + 1.0) * basis->alpha + 0.5;
+      const double Nnl = norm_nl(basis->alpha, basis->b, basis->G, n, l);
+      const double kn = gegen_lead(n, lam);
+      for (int j = 0; j <= 2 * l; ++j) {
+        const int m = (j + 1) / 2;
+        const double kappa = -(kn / std::sqrt(Nnl)) * ylm_norm(l, m) * ((m & 1) ? -1.0 : 1.0) *
+                             legendre_rho(l, m);
+        const bool sin_part = j > 0 && (j % 2 == 0);
+        const double sigma = sin_part ? 1.0 : -1.0;
+        const double w = j == 0 ? 1.0 : (sin_part ? -2.0 : 2.0);
+        const int64_t t = (int64_t)n * L2 + l * l + j;
+        p->h_cs[t] = sigma * kappa;
+        p->h_fw[t] = w * kappa;
+      }
+    }
+  }
+  auto upload_real = [&](const std::vector<double>& v, void** dst) -> hipError_t {
+    hipError_t e = hipMalloc(dst, v.size() * p->rs + 16);
+    if (e != hipSuccess) return e;
+    if (p->rs == 4) {
+      std::vector<float> f(v.begin(), v.end());
+      return hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    }
+    return hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+  };
+  hipError_t e = upload_real(brad, &p->d_beta_rad);
+  if (e == hipSuccess) e = upload_real(bang, &p->d_beta_ang);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_cs, p->T * 8);
+  if (e == hipSuccess) e = hipMemcpy(p->d_cs, p->h_cs.data(), p->T * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_fw, p->T * 8);
+  if (e == hipSuccess) e = hipMemcpy(p->d_fw, p->h_fw.data(), p->T * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    scf_plan_destroy(p);
+    return fail(SCF_ERR_HIP, "plan allocation failed: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return SCF_OK;
+}
+
+void scf_plan_destroy(scf_plan* p) {
+  if (!p) return;
+  if (p->d_beta_rad) (void)hipFree(p->d_beta_rad);
+  if (p->d_beta_ang) (void)hipFree(p->d_beta_ang);
+  if (p->d_cs) (void)hipFree(p->d_cs);
+  if (p->d_fw) (void)hipFree(p->d_fw);
+  delete p;
+}
+
+scf_status scf_workspace_size(const scf_plan* p, int64_t n, int32_t nclusters, size_t* bytes) {
+  if (!p || !bytes) return fail(SCF_ERR_INVALID_ARG, "plan and bytes must be non-null");
+  if (n < 0 || nclusters < 1) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nclusters >= 1");
+  int64_t chunk;
+  int nb = coef_blocks(p, n, &chunk);
+  nb += nclusters;  // batched mode: one extra partial block per cluster boundary
+  *bytes = ws_layout(p, n, nclusters, nb).total + align256((size_t)nclusters * 64 * sizeof(double)) +
+           align256((size_t)(nb + 2 * ((n + 255) / 256 + nclusters)) * 3 * sizeof(int64_t));
+  return SCF_OK;
+}
+
+scf_status scf_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                      const void* m, double* coef, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (n < 0) return fail(SCF_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+  if (!coef) return fail(SCF_ERR_INVALID_ARG, "coef is null");
+  if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(m)))
+    return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
+  size_t need;
+  scf_workspace_size(p, n, 1, &need);
+  if (!ws || ws_bytes < need)
+    return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  int64_t chunk;
+  const int nb = coef_blocks(p, n, &chunk);
+  const WsLayout L = ws_layout(p, n, 1, nb);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  if (p->dtype == SCF_F32)
+    return run_coeffs<float>(p, n, x, y, z, m, coef, w + L.W, w, L, nb, chunk, s);
+  return run_coeffs<double>(p, n, x, y, z, m, coef, w + L.W, w, L, nb, chunk, s);
+}
+
+scf_status scf_forces(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                      const double* coef, const scf_host* host, const double* centre, void* ax,
+                      void* ay, void* az, void* pot, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (n < 0) return fail(SCF_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+  if (!coef) return fail(SCF_ERR_INVALID_ARG, "coef is null");
+  if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(ax) && ptr_ok(ay) && ptr_ok(az)))
+    return fail(SCF_ERR_INVALID_ARG, "particle and output arrays must be non-null");
+  scf_status hs = check_host(host);
+  if (hs != SCF_OK) return hs;
+  const bool with_host = host && host->ncomp > 0;
+  if (with_host && !centre) return fail(SCF_ERR_INVALID_ARG, "centre is null with a host potential");
+  size_t need;
+  scf_workspace_size(p, n, 1, &need);
+  if (!ws || ws_bytes < need)
+    return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  int64_t chunk;
+  const int nb = coef_blocks(p, n, &chunk);
+  const WsLayout L = ws_layout(p, n, 1, nb);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  HIP_TRY(launch_make_w(p->dtype, coef, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_fw, w + L.W, s));
+  double cen[6] = {0, 0, 0, 0, 0, 0};
+  if (with_host) {
+    HostParams<double> hd;
+    fill_host_params(hd, host);
+    double g[3];
+    host_grad<double>(hd, centre[0], centre[1], centre[2], g[0], g[1], g[2]);
+    for (int i = 0; i < 3; ++i) {
+      cen[i] = centre[i];
+      cen[3 + i] = g[i];
+    }
+  }
+  if (p->dtype == SCF_F32) {
+    HostParams<float> hp;
+    fill_host_params(hp, with_host ? host : nullptr);
+    return run_field<float>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, ax, ay,
+                            az, pot, w + L.W, hp, cen, 0, 0.0, 0.0, s);
+  }
+  HostParams<double> hp;
+  fill_host_params(hp, with_host ? host : nullptr);
+  return run_field<double>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, ax, ay, az,
+                           pot, w + L.W, hp, cen, 0, 0.0, 0.0, s);
+}
+
+scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx, void* vy, void* vz,
+                    const void* m, void* ax, void* ay, void* az, uint32_t step_flags,
+                    const scf_host* host, double* centre, double dt, int32_t nsteps,
+                    double* coef_last, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (n < 0 || nsteps < 0) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nsteps >= 0");
+  if (!std::isfinite(dt)) return fail(SCF_ERR_INVALID_ARG, "dt is not finite");
+  if (step_flags & ~SCF_STEP_ACC_VALID) return fail(SCF_ERR_INVALID_ARG, "unknown step flags");
+  if (!centre) return fail(SCF_ERR_INVALID_ARG, "centre is null");
+  if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(vx) && ptr_ok(vy) && ptr_ok(vz) &&
+                 ptr_ok(m) && ptr_ok(ax) && ptr_ok(ay) && ptr_ok(az)))
+    return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
+  scf_status hs = check_host(host);
+  if (hs != SCF_OK) return hs;
+  size_t need;
+  scf_workspace_size(p, n, 1, &need);
+  if (!ws || ws_bytes < need)
+    return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  int64_t chunk;
+  const int nb = coef_blocks(p, n, &chunk);
+  const WsLayout L = ws_layout(p, n, 1, nb);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const bool with_host = host && host->ncomp > 0;
+  HostParams<double> hd;
+  fill_host_params(hd, with_host ? host : nullptr);
+  // centre orbit on the host, double precision, same leapfrog
+  double R[3] = {centre[0], centre[1], centre[2]}, V[3] = {centre[3], centre[4], centre[5]};
+  auto cen_row = [&](double* row) {
+    double g[3] = {0, 0, 0};
+    if (with_host) host_grad<double>(hd, R[0], R[1], R[2], g[0], g[1], g[2]);
+    for (int i = 0; i < 3; ++i) {
+      row[i] = R[i];
+      row[3 + i] = g[i];
+    }
+  };
+  double* coef_int = (double*)(w + L.coef);
+  void* W = w + L.W;
+  const double h = 0.5 * dt;
+  auto go = [&](auto tag) -> scf_status {
+    using Rt = decltype(tag);
+    HostParams<Rt> hp;
+    fill_host_params(hp, with_host ? host : nullptr);
+    double row[6];
+    scf_status st;
+    if (!(step_flags & SCF_STEP_ACC_VALID) || nsteps == 0) {
+      // a(x0) from the particles themselves
+      cen_row(row);
+      st = run_coeffs<Rt>(p, n, x, y, z, m, nsteps == 0 && coef_last ? coef_last : coef_int, W, w, L,
+                          nb, chunk, s);
+      if (st != SCF_OK) return st;
+      st = run_field<Rt>(p, n, x, y, z, vx, vy, vz, ax, ay, az, nullptr, W, hp, row, 0, 0.0, 0.0, s);
+      if (st != SCF_OK) return st;
+    }
+    if (nsteps == 0) return SCF_OK;
+    // opening half kick and drift with the stored accelerations
+    HIP_TRY(launch_kick_drift(p->dtype, n, x, y, z, vx, vy, vz, ax, ay, az, h, dt, s));
+    double gc[3];
+    centre_accel(hd, R, gc);
+    for (int i = 0; i < 3; ++i) V[i] += h * gc[i];
+    for (int i = 0; i < 3; ++i) R[i] += dt * V[i];
+    for (int k = 1; k <= nsteps; ++k) {
+      const bool last = k == nsteps;
+      cen_row(row);
+      st = run_coeffs<Rt>(p, n, x, y, z, m, last && coef_last ? coef_last : coef_int, W, w, L, nb,
+                          chunk, s);
+      if (st != SCF_OK) return st;
+      // closing half kick of step k merged with the opening half kick of
+      // step k+1, then the drift of step k+1
+      st = run_field<Rt>(p, n, x, y, z, vx, vy, vz, ax, ay, az, nullptr, W, hp, row, 1,
+                         last ? h : dt, last ? 0.0 : dt, s);
+      if (st != SCF_OK) return st;
+      centre_accel(hd, R, gc);
+      for (int i = 0; i < 3; ++i) V[i] += (last ? h : dt) * gc[i];
+      if (!last)
+        for (int i = 0; i < 3; ++i) R[i] += dt * V[i];
+    }
+    return SCF_OK;
+  };
+  scf_status st = p->dtype == SCF_F32 ? go(float(0)) : go(double(0));
+  if (st != SCF_OK) return st;
+  for (int i = 0; i < 3; ++i) {
+    centre[i] = R[i];
+    centre[3 + i] = V[i];
+  }
+  return SCF_OK;
+}
+
+scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offsets, void* x, void* y,
+                            void* z, void* vx, void* vy, void* vz, const void* m, void* ax,
+                            void* ay, void* az, uint32_t step_flags, const scf_host* host,
+                            double* centres, double dt, int32_t nsteps, double* coef_last, void* ws,
+                            size_t ws_bytes, void* stream) {
+  (void)p; (void)nclusters; (void)offsets; (void)x; (void)y; (void)z; (void)vx; (void)vy; (void)vz;
+  (void)m; (void)ax; (void)ay; (void)az; (void)step_flags; (void)host; (void)centres; (void)dt;
+  (void)nsteps; (void)coef_last; (void)ws; (void)ws_bytes; (void)stream;
+  return fail(SCF_ERR_UNSUPPORTED, "scf_step_batched: not built yet");
+}
+
+scf_status scf_adjoint_workspace_size(const scf_plan* p, int64_t n, int32_t nsteps, size_t* bytes) {
+  (void)p; (void)n; (void)nsteps; (void)bytes;
+  return fail(SCF_ERR_UNSUPPORTED, "scf_step_adjoint: not built yet");
+}
+
+scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* y0, const void* z0,
+                            const void* vx0, const void* vy0, const void* vz0, const void* m,
+                            const scf_host* host, const double* centre0, double dt, int32_t nsteps,
+                            void* const* lam, double* lam_centre, double* grad_host, void* ws,
+                            size_t ws_bytes, void* stream) {
+  (void)p; (void)n; (void)x0; (void)y0; (void)z0; (void)vx0; (void)vy0; (void)vz0; (void)m;
+  (void)host; (void)centre0; (void)dt; (void)nsteps; (void)lam; (void)lam_centre; (void)grad_host;
+  (void)ws; (void)ws_bytes; (void)stream;
+  return fail(SCF_ERR_UNSUPPORTED, "scf_step_adjoint: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal interfaces of libscf: the per-(dtype, nmax, lmax) kernel engines
+// and the argument blocks their launchers take.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "host_field.h"
+
+namespace scf {
+
+// Kernel arguments of the coefficient (particle-sum) kernel.
+template <typename R>
+struct CoefArgs {
+  const R* x;
+  const R* y;
+  const R* z;
+  const R* m;
+  const int64_t* seg_begin;  // per-block particle range [seg_begin[b], seg_end[b])
+  const int64_t* seg_end;
+  const int32_t* seg_slot;   // per-block output slot (partials row)
+  int64_t begin, chunk, n;   // used when seg_begin == nullptr: block b covers
+                             // [begin + b*chunk, min(begin + (b+1)*chunk, n))
+  const R* beta_rad;         // [(lmax+1)][(NMAXC+1)]  monic Gegenbauer recurrence
+  const R* beta_ang;         // [(lmax+1)][(lmax+1)]   monic Legendre recurrence, [m][l]
+  R* partials;               // [nblocks][T]
+  int T, nmax;
+  R binv, alpha, inv_alpha;
+  int amode;
+};
+
+// Kernel arguments of the field (force / kick-drift) kernel.
+template <typename R>
+struct ForceArgs {
+  R* x;
+  R* y;
+  R* z;
+  R* vx;
+  R* vy;
+  R* vz;
+  R* ax;
+  R* ay;
+  R* az;
+  R* pot;
+  const R* W;         // [(lmax+1)^2][(NMAXC+1)] force weights, n fastest
+  const R* beta_rad;  // as in CoefArgs
+  const R* beta_ang;
+  int64_t n;
+  R binv, alpha, inv_alpha;
+  int amode;
+  R kick, drift;      // step mode: v += kick * a; x += drift * v
+  HostParams<R> host;
+  R cx, cy, cz;       // frame centre R
+  R gcx, gcy, gcz;    // grad psi_host(R) (host, double precision, rounded)
+  // batched mode: per-block cluster id table and per-cluster tables
+  const int32_t* blk_cluster;  // nullable
+  const int64_t* blk_begin;    // particle range of each block (batched mode)
+  const int64_t* blk_end;
+  const double* centre_tab;    // [nclusters][9]: R, grad psi_host(R), unused
+  int64_t W_stride;            // elements between clusters' W tables
+};
+
+// Job descriptions handed to an engine.
+struct Engine {
+  virtual ~Engine() {}
+  virtual int nmaxc() const = 0;
+  virtual int lmax() const = 0;
+  virtual int dtype() const = 0;
+  virtual size_t real_size() const = 0;
+  // number of particles processed per coefficient block-stage
+  virtual int stage_particles() const = 0;
+  // launches the coefficient kernel over nblocks blocks
+  virtual hipError_t launch_coef(const void* args, int nblocks, hipStream_t s) const = 0;
+  // launches the field kernel; mode 0 = forces, 1 = kick/drift step
+  virtual hipError_t launch_force(const void* args, int64_t nblocks, int mode, hipStream_t s) const = 0;
+  virtual const char* describe() const = 0;
+};
+
+Engine* find_engine(int dtype, int nmax, int lmax);
+
+// Small kernels independent of (nmax, lmax).
+hipError_t launch_reduce(int dtype, const void* partials, int nblocks, int T, int nchunks,
+                         double* red1, hipStream_t s);
+hipError_t launch_finalize(int dtype, const double* red1, int nchunks, int T, int nmax, int lmax,
+                           int nmaxc, const double* cs, const double* fw, double* coef, void* W,
+                           hipStream_t s);
+hipError_t launch_make_w(int dtype, const double* coef, int T, int nmax, int lmax, int nmaxc,
+                         const double* fw, void* W, hipStream_t s);
+hipError_t launch_kick_drift(int dtype, int64_t n, void* x, void* y, void* z, void* vx, void* vy,
+                             void* vz, const void* ax, const void* ay, const void* az, double kick,
+                             double drift, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+}  // namespace scf

@@ -1,0 +1,214 @@
+"""Thin ctypes binding of libscf (include/scf.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels
+of ``libscf.so``.  PyTorch provides device memory (tensors) and the current
+stream.  If the library is missing this module raises ImportError-like
+RuntimeError on first use; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscf.so")
+
+F32, F64 = 0, 1
+STEP_ACC_VALID = 1
+HOST_KINDS = {"log": 1, "hernquist": 2, "nfw": 3, "mn": 4, "plummer": 5}
+MAX_HOST_COMP = 8
+
+STATUS = {0: "SCF_OK", 1: "SCF_ERR_INVALID_ARG", 2: "SCF_ERR_UNSUPPORTED", 3: "SCF_ERR_WORKSPACE",
+          4: "SCF_ERR_NONFINITE", 5: "SCF_ERR_HIP"}
+
+
+class ScfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CBasis(C.Structure):
+    _fields_ = [("nmax", C.c_int32), ("lmax", C.c_int32), ("alpha", C.c_double),
+                ("b", C.c_double), ("G", C.c_double)]
+
+
+class CHostComp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("p", C.c_double * 3)]
+
+
+class CHost(C.Structure):
+    _fields_ = [("ncomp", C.c_int32), ("pad", C.c_int32), ("G", C.c_double),
+                ("comp", CHostComp * MAX_HOST_COMP)]
+
+
+_lib = None
+
+# exported functions: name -> (restype, argtypes)
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+SIGNATURES = {
+    "scf_ncoef": (C.c_int64, [C.c_int32, C.c_int32]),
+    "scf_plan_create": (C.c_int, [C.POINTER(_vp), C.POINTER(CBasis), C.c_int32, C.c_uint32]),
+    "scf_plan_destroy": (None, [_vp]),
+    "scf_workspace_size": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scf_coeffs": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "scf_forces": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, C.POINTER(CHost), _dp, _vp, _vp,
+                             _vp, _vp, _vp, C.c_size_t, _vp]),
+    "scf_step": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                           C.c_uint32, C.POINTER(CHost), _dp, C.c_double, C.c_int32, _vp, _vp,
+                           C.c_size_t, _vp]),
+    "scf_step_batched": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), _vp, _vp, _vp, _vp, _vp,
+                                   _vp, _vp, _vp, _vp, _vp, C.c_uint32, C.POINTER(CHost), _dp,
+                                   C.c_double, C.c_int32, _vp, _vp, C.c_size_t, _vp]),
+    "scf_step_adjoint": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   C.POINTER(CHost), _dp, C.c_double, C.c_int32, C.POINTER(_vp),
+                                   _dp, _dp, _vp, C.c_size_t, _vp]),
+    "scf_adjoint_workspace_size": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scf_status_string": (C.c_char_p, [C.c_int]),
+    "scf_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libscf.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libscf.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise ScfError(status, lib().scf_last_error().decode())
+
+
+def ncoef(nmax, lmax):
+    return int(lib().scf_ncoef(nmax, lmax))
+
+
+def make_host(components, G=1.0):
+    """components: list of (kind, params) with kind a name or integer."""
+    h = CHost()
+    if components is None:
+        return h
+    if len(components) > MAX_HOST_COMP:
+        raise ValueError("too many host components")
+    h.ncomp = len(components)
+    h.G = float(G)
+    for i, (kind, params) in enumerate(components):
+        h.comp[i].kind = HOST_KINDS[kind] if isinstance(kind, str) else int(kind)
+        pp = list(params) + [0.0] * (3 - len(params))
+        for k in range(3):
+            h.comp[i].p[k] = float(pp[k])
+    return h
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """An SCF plan: basis tables and kernels for one (basis, dtype)."""
+
+    def __init__(self, nmax, lmax, alpha=1.0, b=1.0, G=1.0, dtype="f32"):
+        self.nmax, self.lmax = int(nmax), int(lmax)
+        self.alpha, self.b, self.G = float(alpha), float(b), float(G)
+        self.dtype = F32 if dtype in ("f32", "float32", F32) else F64
+        self.basis = CBasis(self.nmax, self.lmax, self.alpha, self.b, self.G)
+        self._h = C.c_void_p()
+        _check(lib().scf_plan_create(C.byref(self._h), C.byref(self.basis), self.dtype, 0))
+        self.T = ncoef(self.nmax, self.lmax)
+        self._ws = None
+
+    @property
+    def torch_dtype(self):
+        torch = _torch()
+        return torch.float32 if self.dtype == F32 else torch.float64
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and h.value and _lib is not None:
+            _lib.scf_plan_destroy(h)
+            self._h = None
+
+    def workspace(self, n, nclusters=1, device=None):
+        torch = _torch()
+        need = C.c_size_t()
+        _check(lib().scf_workspace_size(self._h, int(n), int(nclusters), C.byref(need)))
+        if self._ws is None or self._ws.numel() < need.value:
+            self._ws = torch.empty(max(need.value, 256), dtype=torch.uint8,
+                                   device=device or torch.device("cuda"))
+        return self._ws
+
+    def _check_arrays(self, *ts):
+        for t in ts:
+            if t is None:
+                continue
+            if t.dtype != self.torch_dtype or not t.is_cuda or not t.is_contiguous():
+                raise TypeError(f"expected contiguous {self.torch_dtype} CUDA tensors")
+
+    def coeffs(self, x, y, z, m, out=None):
+        torch = _torch()
+        self._check_arrays(x, y, z, m)
+        n = x.numel()
+        if out is None:
+            out = torch.empty(self.T, dtype=torch.float64, device=x.device)
+        ws = self.workspace(n, device=x.device)
+        _check(lib().scf_coeffs(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(m), _ptr(out),
+                                _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def forces(self, x, y, z, coef, host=None, centre=None, pot=False):
+        torch = _torch()
+        self._check_arrays(x, y, z)
+        n = x.numel()
+        ax, ay, az = (torch.empty_like(x) for _ in range(3))
+        p = torch.empty_like(x) if pot else None
+        h = make_host(host[0], host[1]) if host is not None else None
+        cen = (C.c_double * 3)(*[float(v) for v in centre[:3]]) if centre is not None else None
+        ws = self.workspace(n, device=x.device)
+        _check(lib().scf_forces(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(coef),
+                                C.byref(h) if h is not None else None,
+                                C.cast(cen, _dp) if cen is not None else None, _ptr(ax),
+                                _ptr(ay), _ptr(az), _ptr(p), _ptr(ws), ws.numel(), _stream()))
+        return (ax, ay, az, p) if pot else (ax, ay, az)
+
+    def step(self, st, m, dt, nsteps, host=None, centre=None, acc=None, coef_last=None):
+        """Advance st = [x, y, z, vx, vy, vz] in place.  acc = [ax, ay, az]
+        (in/out; pass the previous call's to skip the start-up evaluation).
+        Returns (centre (6,) numpy, acc)."""
+        torch = _torch()
+        self._check_arrays(*st, m)
+        n = st[0].numel()
+        acc_valid = acc is not None
+        if acc is None:
+            acc = [torch.empty_like(st[0]) for _ in range(3)]
+        cen = (C.c_double * 6)(*[float(v) for v in (centre if centre is not None else np.zeros(6))])
+        h = make_host(host[0], host[1]) if host is not None else None
+        ws = self.workspace(n, device=st[0].device)
+        _check(lib().scf_step(self._h, n, *[_ptr(t) for t in st], _ptr(m), *[_ptr(t) for t in acc],
+                              STEP_ACC_VALID if acc_valid else 0,
+                              C.byref(h) if h is not None else None, C.cast(cen, _dp), float(dt),
+                              int(nsteps), _ptr(coef_last), _ptr(ws), ws.numel(), _stream()))
+        return np.array(cen[:]), acc

@@ -1,0 +1,231 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (fixed before the kernels were written):
+  coefficients  max_t |da_t| / max_t |a_t|                  <= 1e-5 (FP32), 1e-11 (FP64)
+  forces        max_i |dg_i| / (|g_i| + median_j |g_j|)     <= 1e-5 (FP32), 1e-11 (FP64)
+The oracle is fed the same FP32-representable inputs, upcast to double.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2602_13385_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-11}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2602_13385_amd import scf
+    scf.lib()
+    return scf
+
+
+def _dev(torch, arr, dtype):
+    td = torch.float32 if dtype == "f32" else torch.float64
+    return torch.as_tensor(np.ascontiguousarray(arr), dtype=td, device="cuda")
+
+
+def _rounded(arr, dtype):
+    return np.asarray(arr, dtype=np.float32).astype(np.float64) if dtype == "f32" else np.asarray(arr, np.float64)
+
+
+def coef_err(a, ref):
+    return np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def force_err(g, ref):
+    mag = np.sqrt((ref ** 2).sum(0))
+    d = np.sqrt(((g - ref) ** 2).sum(0))
+    return (d / (mag + np.median(mag))).max()
+
+
+def _gpu_coeffs(torch, S, plan, pos, m, dtype):
+    x, y, z = (_dev(torch, pos[i], dtype) for i in range(3))
+    c = plan.coeffs(x, y, z, _dev(torch, m, dtype))
+    torch.cuda.synchronize()
+    return c.cpu().numpy()
+
+
+CASES = [  # (nmax, lmax, alpha, n, generator)
+    (6, 4, 1.0, 10_000, "plummer"),
+    (10, 6, 1.0, 20_011, "plummer"),
+    (16, 10, 1.0, 30_001, "hernquist"),
+    (10, 5, 1.0, 4_099, "ball"),
+    (8, 3, 1.0, 3_001, "ball"),  # generic instance (runtime nmax < compiled bound)
+    (6, 4, 0.5, 5_003, "plummer"),
+    (10, 6, 0.8, 5_003, "plummer"),
+]
+
+
+def _gen(kind, n, seed):
+    if kind == "plummer":
+        return I.plummer(n, seed)
+    if kind == "hernquist":
+        return I.hernquist(n, seed)
+    return I.uniform_ball(n, seed)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"n{c[0]}l{c[1]}a{c[2]}N{c[3]}")
+def test_coeffs_and_forces_match_oracle(torch, S, O, case, dtype):
+    nmax, lmax, alpha, n, kind = case
+    print(f"[parity] nmax={nmax} lmax={lmax} alpha={alpha} N={n} {dtype}", flush=True)
+    p = _gen(kind, n, 700 + n % 97)
+    pos = _rounded(p.pos, dtype)
+    m = _rounded(p.mass, dtype)
+    B = O.basis(nmax, lmax, alpha=alpha)
+    ref = O.coeffs(B, *pos, m)
+    plan = S.Plan(nmax, lmax, alpha=alpha, dtype=dtype)
+    c = _gpu_coeffs(torch, S, plan, pos, m, dtype)
+    assert coef_err(c, ref) <= TOL[dtype], coef_err(c, ref)
+    # forces from the reference coefficients, at a sample of the particles
+    k = min(n, 2000)
+    sub = pos[:, :k]
+    Pref, gref = O.field(B, ref, *sub)
+    x, y, z = (_dev(torch, sub[i], dtype) for i in range(3))
+    ax, ay, az, pot = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), pot=True)
+    torch.cuda.synchronize()
+    g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
+    assert force_err(g, gref) <= TOL[dtype], force_err(g, gref)
+    P = pot.cpu().numpy().astype(np.float64)
+    assert np.abs(P - Pref).max() / np.abs(Pref).max() <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_forces_with_host_tidal_field(torch, S, O, dtype):
+    p = I.plummer(3000, 31)
+    pos = _rounded(p.pos, dtype)
+    m = _rounded(p.mass, dtype)
+    comps = [("hernquist", (1.11955, 1.0)), ("mn", (11.8372, 3.0, 0.28)), ("nfw", (124.107, 15.626))]
+    Hc = O.host([(O.HOST_HERNQUIST, (1.11955, 1.0)), (O.HOST_MN, (11.8372, 3.0, 0.28)),
+                 (O.HOST_NFW, (124.107, 15.626))])
+    centre = np.array([18.0, -4.0, 2.5])
+    B = O.basis(10, 6)
+    ref = O.coeffs(B, *pos, m)
+    _, gscf = O.field(B, ref, *pos)
+    _, g0, _ = O.host_eval(Hc, centre)
+    gh = np.stack([O.host_eval(Hc, centre + pos[:, i])[1] for i in range(pos.shape[1])], axis=1)
+    gref = gscf - gh + g0[:, None]
+    plan = S.Plan(10, 6, dtype=dtype)
+    x, y, z = (_dev(torch, pos[i], dtype) for i in range(3))
+    ax, ay, az = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), host=(comps, 1.0),
+                             centre=centre)
+    torch.cuda.synchronize()
+    g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
+    assert force_err(g, gref) <= TOL[dtype], force_err(g, gref)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_edge_cases(torch, S, O, dtype):
+    plan = S.Plan(6, 4, dtype=dtype)
+    B = O.basis(6, 4)
+    td = torch.float32 if dtype == "f32" else torch.float64
+    e = torch.empty(0, dtype=td, device="cuda")
+    c = plan.coeffs(e, e, e, e)
+    torch.cuda.synchronize()
+    assert (c.cpu().numpy() == 0).all()
+    ax, ay, az = plan.forces(e, e, e, c)
+    assert ax.numel() == 0
+    # one particle; a particle exactly at the origin; particles on the poles
+    pos = np.array([[0.0, 0.0, 0.0, 0.3, 1.0], [0.0, 0.0, 0.0, -0.2, 0.5], [0.0, 1.5, -2.0, 0.1, -0.7]])
+    m = np.array([0.2, 0.3, 0.1, 0.25, 0.15])
+    for k in (1, 5):
+        ref = O.coeffs(B, *pos[:, :k], m[:k])
+        cg = _gpu_coeffs(torch, S, plan, _rounded(pos[:, :k], dtype), _rounded(m[:k], dtype), dtype)
+        assert coef_err(cg, ref) <= TOL[dtype]
+    ref = O.coeffs(B, *pos, m)
+    _, gref = O.field(B, ref, *pos)
+    x, y, z = (_dev(torch, pos[i], dtype) for i in range(3))
+    ax, ay, az = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"))
+    torch.cuda.synchronize()
+    g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
+    assert np.isfinite(g).all()
+    assert (g[:, 0] == 0).all()  # the origin gets zero SCF force
+    assert force_err(g, gref) <= TOL[dtype]
+
+
+def test_coefficients_are_deterministic(torch, S):
+    p = I.plummer(50_000, 5)
+    plan = S.Plan(10, 6)
+    x, y, z, m = (_dev(torch, a, "f32") for a in (*p.pos, p.mass))
+    c1 = plan.coeffs(x, y, z, m).cpu().numpy()
+    c2 = plan.coeffs(x, y, z, m).cpu().numpy()
+    assert np.array_equal(c1, c2)
+
+
+def test_hernquist_quadrature_closed_form(torch, S):
+    # the exact pin, through the GPU path: a_000 = 1/sqrt(3), others 0
+    q = I.quadrature_sphere("hernquist", 1.0, nr=40, nmu=24, nphi=24)
+    plan = S.Plan(16, 10, dtype="f64")
+    c = _gpu_coeffs(torch, S, plan, q.pos, q.mass, "f64")
+    assert c[0] == pytest.approx(1 / math.sqrt(3), rel=1e-12)
+    assert np.abs(c[1:]).max() < 1e-12
+    plan32 = S.Plan(16, 10, dtype="f32")
+    c32 = _gpu_coeffs(torch, S, plan32, _rounded(q.pos, "f32"), _rounded(q.mass, "f32"), "f32")
+    assert abs(c32[0] - 1 / math.sqrt(3)) < 1e-5 and np.abs(c32[1:]).max() < 1e-5
+
+
+STEP_CASES = [  # (nmax, lmax, n, host, centre, dt, nsteps)
+    (6, 4, 10_000, None, np.zeros(6), 0.01, 3),
+    (10, 6, 20_000, [("log", (1.5, 1.0))], np.array([20.0, 0, 0, 0, I.LOG_VC_20, 0]), 0.005, 3),
+    (10, 6, 8_000, [("nfw", (232.98, 20.0))], np.array([20.0, 0, 0, 0.1, 1.4, 0.3]), 0.005, 4),
+]
+
+
+def _ohost(O, comps):
+    if comps is None:
+        return None
+    kinds = {"log": O.HOST_LOG, "hernquist": O.HOST_HERNQUIST, "nfw": O.HOST_NFW, "mn": O.HOST_MN,
+             "plummer": O.HOST_PLUMMER}
+    return O.host([(kinds[k], p) for k, p in comps])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("case", STEP_CASES, ids=lambda c: f"n{c[0]}l{c[1]}N{c[2]}")
+def test_step_matches_oracle(torch, S, O, case, dtype):
+    nmax, lmax, n, comps, centre, dt, nsteps = case
+    print(f"[step parity] nmax={nmax} lmax={lmax} N={n} {dtype} host={comps}", flush=True)
+    p = I.plummer(n, 900 + nsteps)
+    st0 = _rounded(p.state(), dtype)
+    m = _rounded(p.mass, dtype)
+    B = O.basis(nmax, lmax)
+    Ho = _ohost(O, comps)
+    st_ref, cen_ref, coef_ref, acc_ref = O.step(B, Ho, st0, m, centre, dt, nsteps, want_acc=True)
+    plan = S.Plan(nmax, lmax, dtype=dtype)
+    st = [_dev(torch, st0[i], dtype) for i in range(6)]
+    md = _dev(torch, m, dtype)
+    coef = torch.empty(plan.T, dtype=torch.float64, device="cuda")
+    cen, acc = plan.step(st, md, dt, nsteps, host=(comps, 1.0) if comps else None, centre=centre,
+                         coef_last=coef)
+    torch.cuda.synchronize()
+    out = np.stack([t.cpu().numpy() for t in st]).astype(np.float64)
+    a = np.stack([t.cpu().numpy() for t in acc]).astype(np.float64)
+    assert np.allclose(cen, cen_ref, rtol=0, atol=1e-12)
+    tol = TOL[dtype]
+    for rows in (slice(0, 3), slice(3, 6)):
+        d = np.abs(out[rows] - st_ref[rows]).max() / np.abs(st_ref[rows]).max()
+        assert d <= tol, d
+    assert coef_err(coef.cpu().numpy(), coef_ref) <= tol
+    assert force_err(a, acc_ref) <= 2 * tol, force_err(a, acc_ref)
+    # a second call continuing with the returned accelerations equals one
+    # longer call
+    st2 = [_dev(torch, st0[i], dtype) for i in range(6)]
+    cenA, accA = plan.step(st2, md, dt, 1, host=(comps, 1.0) if comps else None, centre=centre)
+    cenB, accB = plan.step(st2, md, dt, nsteps - 1, host=(comps, 1.0) if comps else None,
+                           centre=cenA, acc=accA)
+    torch.cuda.synchronize()
+    out2 = np.stack([t.cpu().numpy() for t in st2]).astype(np.float64)
+    split_tol = 1e-6 if dtype == "f32" else 1e-13
+    assert np.abs(out2 - out).max() <= split_tol * np.abs(out).max()
