@@ -174,6 +174,20 @@ scf_status scf_step_adjoint(scf_plan* plan, int64_t n, const void* x0, const voi
 scf_status scf_adjoint_workspace_size(const scf_plan* plan, int64_t n, int32_t nsteps,
                                       size_t* bytes);
 
+/* Kernel timing (tracing): when enabled, every kernel the plan launches is
+ * bracketed by HIP events on its stream; scf_profile_read synchronises on
+ * those events and returns, per kernel kind, the launch count and the summed
+ * event-to-event duration in milliseconds since the last read, then resets.
+ * out must hold SCF_KERNEL_KINDS entries. */
+#define SCF_KERNEL_KINDS 12
+typedef struct {
+  int32_t kind, count;
+  double total_ms;
+} scf_kernel_time;
+scf_status scf_profile_enable(scf_plan* plan, int32_t enable);
+scf_status scf_profile_read(scf_plan* plan, scf_kernel_time* out);
+const char* scf_kernel_name(int32_t kind);
+
 const char* scf_status_string(scf_status status);
 const char* scf_last_error(void);
 

@@ -52,6 +52,8 @@ def lib():
         build()
         L = C.CDLL(LIB_PATH)
         dp = C.POINTER(C.c_double)
+        L.orc_num_threads.restype = C.c_int32
+        L.orc_num_threads.argtypes = []
         L.orc_ncoef.restype = C.c_int64
         L.orc_ncoef.argtypes = [C.c_int32, C.c_int32]
         L.orc_gegenbauer.restype = C.c_double
@@ -110,6 +112,10 @@ def host(components, G=1.0):
         for k in range(3):
             h.comp[i].p[k] = float(pp[k])
     return h
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def ncoef(nmax, lmax):

@@ -58,6 +58,14 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+int32_t orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int64_t orc_ncoef(int32_t nmax, int32_t lmax) {
   if (nmax < 0 || lmax < 0) return 0;
   return (int64_t)(nmax + 1) * (lmax + 1) * (lmax + 1);

@@ -180,9 +180,43 @@ struct scf_plan {
   double* d_cs = nullptr;
   double* d_fw = nullptr;
   std::vector<double> h_cs, h_fw;
+  // kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
 };
 
 namespace {
+
+enum Kind { K_COEF = 0, K_REDUCE, K_FINALIZE, K_FIELD, K_STEP_FIELD, K_KICK, K_MAKE_W, K_FILL,
+            K_BATCH_COEF, K_BATCH_FIELD, K_ADJ, K_OTHER };
+const char* kKindNames[SCF_KERNEL_KINDS] = {"coef", "reduce", "finalize", "field", "field_step",
+                                            "kick_drift", "make_w", "fill", "batched_coef",
+                                            "batched_field", "adjoint", "other"};
+
+// brackets one launch with events when the plan's timing is on
+struct Timed {
+  scf_plan* p;
+  hipStream_t s;
+  int kind;
+  hipEvent_t b = nullptr;
+  Timed(scf_plan* p_, hipStream_t s_, int k) : p(p_), s(s_), kind(k) {
+    if (p && p->prof && p->ev_next + 2 <= p->ev_pool.size()) {
+      hipEvent_t a = p->ev_pool[p->ev_next++];
+      b = p->ev_pool[p->ev_next++];
+      (void)hipEventRecord(a, s);
+      p->recs.push_back({kind, a, b});
+    }
+  }
+  ~Timed() {
+    if (b) (void)hipEventRecord(b, s);
+  }
+};
 
 int coef_blocks(const scf_plan* p, int64_t n, int64_t* chunk) {
   if (n <= 0) {
@@ -290,7 +324,11 @@ scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
                       int64_t chunk, hipStream_t s) {
   if (n == 0) {
     // empty particle set: all coefficients vanish
-    if (coef) HIP_TRY(launch_fill(coef, p->T, 0.0, s));
+    if (coef) {
+      Timed t(p, s, K_FILL);
+      HIP_TRY(launch_fill(coef, p->T, 0.0, s));
+    }
+    Timed t(p, s, K_MAKE_W);
     HIP_TRY(launch_make_w(p->dtype, coef ? coef : (double*)(ws + L.coef), (int)p->T, p->nmax,
                           p->lmax, p->nmaxc, p->d_fw, W, s));
     return SCF_OK;
@@ -305,12 +343,21 @@ scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
   ca.chunk = chunk;
   ca.n = n;
   ca.partials = (R*)(ws + L.partials);
-  HIP_TRY(p->eng->launch_coef(&ca, nb, s));
+  {
+    Timed t(p, s, K_COEF);
+    HIP_TRY(p->eng->launch_coef(&ca, nb, s));
+  }
   double* red1 = (double*)(ws + L.red1);
   const int nch = std::min(kReduceChunks, nb);
-  HIP_TRY(launch_reduce(p->dtype, ca.partials, nb, (int)p->T, nch, red1, s));
-  HIP_TRY(launch_finalize(p->dtype, red1, nch, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
-                          p->d_fw, coef, W, s));
+  {
+    Timed t(p, s, K_REDUCE);
+    HIP_TRY(launch_reduce(p->dtype, ca.partials, nb, (int)p->T, nch, red1, s));
+  }
+  {
+    Timed t(p, s, K_FINALIZE);
+    HIP_TRY(launch_finalize(p->dtype, red1, nch, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
+                            p->d_fw, coef, W, s));
+  }
   return SCF_OK;
 }
 
@@ -343,6 +390,7 @@ scf_status run_field(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx
   fa.gcx = R(cen ? cen[3] : 0.0);
   fa.gcy = R(cen ? cen[4] : 0.0);
   fa.gcz = R(cen ? cen[5] : 0.0);
+  Timed t(p, s, mode == 0 ? K_FIELD : K_STEP_FIELD);
   HIP_TRY(p->eng->launch_force(&fa, (n + 255) / 256, mode, s));
   return SCF_OK;
 }
@@ -371,6 +419,36 @@ const char* scf_status_string(scf_status st) {
 }
 
 const char* scf_last_error(void) { return g_last_error.c_str(); }
+
+const char* scf_kernel_name(int32_t kind) {
+  if (kind < 0 || kind >= SCF_KERNEL_KINDS) return "unknown";
+  return kKindNames[kind];
+}
+
+scf_status scf_profile_enable(scf_plan* p, int32_t enable) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (enable && p->ev_pool.empty()) {
+    p->ev_pool.resize(8192);
+    for (auto& e : p->ev_pool) HIP_TRY(hipEventCreate(&e));
+  }
+  p->prof = enable != 0;
+  return SCF_OK;
+}
+
+scf_status scf_profile_read(scf_plan* p, scf_kernel_time* out) {
+  if (!p || !out) return fail(SCF_ERR_INVALID_ARG, "plan and out must be non-null");
+  for (int k = 0; k < SCF_KERNEL_KINDS; ++k) out[k] = scf_kernel_time{k, 0, 0.0};
+  for (const auto& r : p->recs) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    out[r.kind].count += 1;
+    out[r.kind].total_ms += ms;
+  }
+  p->recs.clear();
+  p->ev_next = 0;
+  return SCF_OK;
+}
 
 scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype, uint32_t flags) {
   if (!out || !basis) return fail(SCF_ERR_INVALID_ARG, "plan and basis must be non-null");
@@ -451,6 +529,7 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
 
 void scf_plan_destroy(scf_plan* p) {
   if (!p) return;
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->d_beta_rad) (void)hipFree(p->d_beta_rad);
   if (p->d_beta_ang) (void)hipFree(p->d_beta_ang);
   if (p->d_cs) (void)hipFree(p->d_cs);
@@ -511,7 +590,10 @@ scf_status scf_forces(scf_plan* p, int64_t n, const void* x, const void* y, cons
   const WsLayout L = ws_layout(p, n, 1, nb);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
-  HIP_TRY(launch_make_w(p->dtype, coef, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_fw, w + L.W, s));
+  {
+    Timed t(p, s, K_MAKE_W);
+    HIP_TRY(launch_make_w(p->dtype, coef, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_fw, w + L.W, s));
+  }
   double cen[6] = {0, 0, 0, 0, 0, 0};
   if (with_host) {
     HostParams<double> hd;
@@ -591,7 +673,10 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
     }
     if (nsteps == 0) return SCF_OK;
     // opening half kick and drift with the stored accelerations
-    HIP_TRY(launch_kick_drift(p->dtype, n, x, y, z, vx, vy, vz, ax, ay, az, h, dt, s));
+    {
+      Timed t(p, s, K_KICK);
+      HIP_TRY(launch_kick_drift(p->dtype, n, x, y, z, vx, vy, vz, ax, ay, az, h, dt, s));
+    }
     double gc[3];
     centre_accel(hd, R, gc);
     for (int i = 0; i < 3; ++i) V[i] += h * gc[i];

@@ -40,6 +40,13 @@ class CHostComp(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("p", C.c_double * 3)]
 
 
+class CKernelTime(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("count", C.c_int32), ("total_ms", C.c_double)]
+
+
+KERNEL_KINDS = 12
+
+
 class CHost(C.Structure):
     _fields_ = [("ncomp", C.c_int32), ("pad", C.c_int32), ("G", C.c_double),
                 ("comp", CHostComp * MAX_HOST_COMP)]
@@ -68,6 +75,9 @@ SIGNATURES = {
                                    C.POINTER(CHost), _dp, C.c_double, C.c_int32, C.POINTER(_vp),
                                    _dp, _dp, _vp, C.c_size_t, _vp]),
     "scf_adjoint_workspace_size": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
+    "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
+    "scf_kernel_name": (C.c_char_p, [C.c_int32]),
     "scf_status_string": (C.c_char_p, [C.c_int]),
     "scf_last_error": (C.c_char_p, []),
 }
@@ -151,6 +161,17 @@ class Plan:
         if h and h.value and _lib is not None:
             _lib.scf_plan_destroy(h)
             self._h = None
+
+    def profile(self, enable=True):
+        """Turn per-kernel HIP-event timing on or off."""
+        _check(lib().scf_profile_enable(self._h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """{kernel name: (launches, total ms)} since the last call."""
+        arr = (CKernelTime * KERNEL_KINDS)()
+        _check(lib().scf_profile_read(self._h, C.cast(arr, C.c_void_p)))
+        return {lib().scf_kernel_name(k).decode(): (arr[k].count, arr[k].total_ms)
+                for k in range(KERNEL_KINDS) if arr[k].count}
 
     def workspace(self, n, nclusters=1, device=None):
         torch = _torch()
