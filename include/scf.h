@@ -174,6 +174,19 @@ scf_status scf_step_adjoint(scf_plan* plan, int64_t n, const void* x0, const voi
 scf_status scf_adjoint_workspace_size(const scf_plan* plan, int64_t n, int32_t nsteps,
                                       size_t* bytes);
 
+/* Launch configuration.  The coefficient kernel has several compiled
+ * variants (lanes per particle in the basis phase, waves per block).
+ * scf_autotune times each on the given particles (synchronising the stream)
+ * and keeps the fastest for the plan; best_ms (nullable) receives its time.
+ * Variants give results that agree to rounding (the particle sums are grouped
+ * differently); a fixed variant is bitwise reproducible. */
+int32_t scf_plan_num_variants(const scf_plan* plan);
+int32_t scf_plan_variant(const scf_plan* plan);
+scf_status scf_plan_set_variant(scf_plan* plan, int32_t variant);
+const char* scf_plan_describe(const scf_plan* plan);
+scf_status scf_autotune(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
+                        const void* m, void* ws, size_t ws_bytes, void* stream, double* best_ms);
+
 /* Kernel timing (tracing): when enabled, every kernel the plan launches is
  * bracketed by HIP events on its stream; scf_profile_read synchronises on
  * those events and returns, per kernel kind, the launch count and the summed

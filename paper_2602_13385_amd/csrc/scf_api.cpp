@@ -174,6 +174,9 @@ struct scf_plan {
   int64_t T;
   int amode;
   Engine* eng;
+  int coef_variant = 0;
+  int num_cu = 256;
+  int resident[8] = {1, 1, 1, 1, 1, 1, 1, 1};  // resident wave-units per CU per variant
   size_t rs;  // sizeof real
   void* d_beta_rad = nullptr;
   void* d_beta_ang = nullptr;
@@ -218,17 +221,37 @@ struct Timed {
   }
 };
 
-int coef_blocks(const scf_plan* p, int64_t n, int64_t* chunk) {
+// Coefficient launch geometry: one resident round of wave-units (the
+// occupancy of the variant times the CU count), each taking an even share of
+// the P-particle stages; returns the unit count and sets *stages.
+int coef_units_v(const scf_plan* p, int64_t n, int v, int64_t* stages) {
   if (n <= 0) {
-    *chunk = 0;
+    *stages = 0;
     return 0;
   }
-  const int P = p->eng->stage_particles();
-  const int64_t stages = (n + P - 1) / P;
-  const int64_t target = 2048;
-  const int64_t per = (stages + target - 1) / target;
-  *chunk = per * P;
-  return (int)((n + *chunk - 1) / *chunk);
+  const int P = p->eng->stage_particles(v);
+  *stages = (n + P - 1) / P;
+  const int64_t cap = (int64_t)p->resident[v] * p->num_cu;
+  return (int)std::min<int64_t>(*stages, std::max<int64_t>(cap, 1));
+}
+
+int coef_units(const scf_plan* p, int64_t n, int64_t* stages) {
+  return coef_units_v(p, n, p->coef_variant, stages);
+}
+
+// partial-sum rows of the current variant
+int coef_rows(const scf_plan* p, int units) {
+  return units * p->eng->rows_per_unit(p->coef_variant);
+}
+
+// largest partial-row count over the coefficient variants (workspace sizing)
+int coef_blocks_max(const scf_plan* p, int64_t n) {
+  int nb = 0;
+  for (int v = 0; v < p->eng->coef_variants(); ++v) {
+    int64_t st;
+    nb = std::max(nb, coef_units_v(p, n, v, &st) * p->eng->rows_per_unit(v));
+  }
+  return nb;
 }
 
 constexpr int kReduceChunks = 16;
@@ -238,6 +261,7 @@ struct WsLayout {
 };
 
 WsLayout ws_layout(const scf_plan* p, int64_t n, int nclusters, int nblocks) {
+  nblocks = std::max(nblocks, coef_blocks_max(p, n));  // layout independent of the variant
   WsLayout L;
   size_t off = 0;
   L.partials = off;
@@ -320,8 +344,10 @@ void fill_coef_common(CoefArgs<R>& ca, const scf_plan* p) {
 // coefficients of n particles into coef (device) and force weights W (device)
 template <typename R>
 scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
-                      const void* m, double* coef, void* W, char* ws, const WsLayout& L, int nb,
-                      int64_t chunk, hipStream_t s) {
+                      const void* m, double* coef, void* W, char* ws, const WsLayout& L, hipStream_t s) {
+  int64_t stages;
+  const int units = coef_units(p, n, &stages);
+  const int nb = coef_rows(p, units);
   if (n == 0) {
     // empty particle set: all coefficients vanish
     if (coef) {
@@ -340,12 +366,13 @@ scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
   ca.z = (const R*)z;
   ca.m = (const R*)m;
   ca.begin = 0;
-  ca.chunk = chunk;
+  ca.stages = stages;
   ca.n = n;
   ca.partials = (R*)(ws + L.partials);
+  ca.nunits = units;
   {
     Timed t(p, s, K_COEF);
-    HIP_TRY(p->eng->launch_coef(&ca, nb, s));
+    HIP_TRY(p->eng->launch_coef(&ca, units, p->coef_variant, s));
   }
   double* red1 = (double*)(ws + L.red1);
   const int nch = std::min(kReduceChunks, nb);
@@ -425,6 +452,69 @@ const char* scf_kernel_name(int32_t kind) {
   return kKindNames[kind];
 }
 
+int32_t scf_plan_num_variants(const scf_plan* p) { return p ? p->eng->coef_variants() : 0; }
+
+int32_t scf_plan_variant(const scf_plan* p) { return p ? p->coef_variant : -1; }
+
+scf_status scf_plan_set_variant(scf_plan* p, int32_t v) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (v < 0 || v >= p->eng->coef_variants())
+    return fail(SCF_ERR_INVALID_ARG, "variant %d outside [0, %d)", v, p->eng->coef_variants());
+  p->coef_variant = v;
+  return SCF_OK;
+}
+
+const char* scf_plan_describe(const scf_plan* p) { return p ? p->eng->describe() : ""; }
+
+scf_status scf_autotune(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                        const void* m, void* ws, size_t ws_bytes, void* stream, double* best_ms) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (n <= 0) return SCF_OK;
+  if (!(x && y && z && m)) return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
+  size_t need;
+  scf_workspace_size(p, n, 1, &need);
+  if (!ws || ws_bytes < need)
+    return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double* coef = (double*)((char*)ws + ws_layout(p, n, 1, 0).coef);
+  const int saved = p->coef_variant;
+  const bool prof = p->prof;
+  p->prof = false;
+  int best = saved;
+  float bms = 1e30f;
+  for (int v = 0; v < p->eng->coef_variants(); ++v) {
+    p->coef_variant = v;
+    float tot = 0.f;
+    for (int rep = 0; rep < 4; ++rep) {
+      HIP_TRY(hipEventRecord(e0, s));
+      scf_status st = scf_coeffs(p, n, x, y, z, m, coef, ws, ws_bytes, stream);
+      if (st != SCF_OK) {
+        p->coef_variant = saved;
+        p->prof = prof;
+        return st;
+      }
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tot += ms;  // the first repetition warms up
+    }
+    if (tot < bms) {
+      bms = tot;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->coef_variant = best;
+  p->prof = prof;
+  if (best_ms) *best_ms = bms / 3.0;
+  return SCF_OK;
+}
+
 scf_status scf_profile_enable(scf_plan* p, int32_t enable) {
   if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
   if (enable && p->ev_pool.empty()) {
@@ -475,6 +565,12 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
   p->amode = basis->alpha == 1.0 ? 0 : (basis->alpha == 0.5 ? 1 : 2);
   p->eng = eng;
   p->rs = eng->real_size();
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess && prop.multiProcessorCount > 0)
+      p->num_cu = prop.multiProcessorCount;
+    for (int v = 0; v < eng->coef_variants() && v < 8; ++v) p->resident[v] = eng->max_resident_units(v);
+  }
   const int L1 = p->lmax + 1, NW = p->nmaxc + 1;
   std::vector<double> brad((size_t)L1 * NW, 0.0), bang((size_t)L1 * L1, 0.0);
   for (int l = 0; l <= p->lmax; ++l) {
@@ -540,8 +636,7 @@ void scf_plan_destroy(scf_plan* p) {
 scf_status scf_workspace_size(const scf_plan* p, int64_t n, int32_t nclusters, size_t* bytes) {
   if (!p || !bytes) return fail(SCF_ERR_INVALID_ARG, "plan and bytes must be non-null");
   if (n < 0 || nclusters < 1) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nclusters >= 1");
-  int64_t chunk;
-  int nb = coef_blocks(p, n, &chunk);
+  int nb = coef_blocks_max(p, n);
   nb += nclusters;  // batched mode: one extra partial block per cluster boundary
   *bytes = ws_layout(p, n, nclusters, nb).total + align256((size_t)nclusters * 64 * sizeof(double)) +
            align256((size_t)(nb + 2 * ((n + 255) / 256 + nclusters)) * 3 * sizeof(int64_t));
@@ -559,14 +654,12 @@ scf_status scf_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
   scf_workspace_size(p, n, 1, &need);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  int64_t chunk;
-  const int nb = coef_blocks(p, n, &chunk);
-  const WsLayout L = ws_layout(p, n, 1, nb);
+  const WsLayout L = ws_layout(p, n, 1, 0);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   if (p->dtype == SCF_F32)
-    return run_coeffs<float>(p, n, x, y, z, m, coef, w + L.W, w, L, nb, chunk, s);
-  return run_coeffs<double>(p, n, x, y, z, m, coef, w + L.W, w, L, nb, chunk, s);
+    return run_coeffs<float>(p, n, x, y, z, m, coef, w + L.W, w, L, s);
+  return run_coeffs<double>(p, n, x, y, z, m, coef, w + L.W, w, L, s);
 }
 
 scf_status scf_forces(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
@@ -585,9 +678,7 @@ scf_status scf_forces(scf_plan* p, int64_t n, const void* x, const void* y, cons
   scf_workspace_size(p, n, 1, &need);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  int64_t chunk;
-  const int nb = coef_blocks(p, n, &chunk);
-  const WsLayout L = ws_layout(p, n, 1, nb);
+  const WsLayout L = ws_layout(p, n, 1, 0);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   {
@@ -635,9 +726,7 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
   scf_workspace_size(p, n, 1, &need);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  int64_t chunk;
-  const int nb = coef_blocks(p, n, &chunk);
-  const WsLayout L = ws_layout(p, n, 1, nb);
+  const WsLayout L = ws_layout(p, n, 1, 0);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   const bool with_host = host && host->ncomp > 0;
@@ -665,8 +754,7 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
     if (!(step_flags & SCF_STEP_ACC_VALID) || nsteps == 0) {
       // a(x0) from the particles themselves
       cen_row(row);
-      st = run_coeffs<Rt>(p, n, x, y, z, m, nsteps == 0 && coef_last ? coef_last : coef_int, W, w, L,
-                          nb, chunk, s);
+      st = run_coeffs<Rt>(p, n, x, y, z, m, nsteps == 0 && coef_last ? coef_last : coef_int, W, w, L, s);
       if (st != SCF_OK) return st;
       st = run_field<Rt>(p, n, x, y, z, vx, vy, vz, ax, ay, az, nullptr, W, hp, row, 0, 0.0, 0.0, s);
       if (st != SCF_OK) return st;
@@ -684,8 +772,7 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
     for (int k = 1; k <= nsteps; ++k) {
       const bool last = k == nsteps;
       cen_row(row);
-      st = run_coeffs<Rt>(p, n, x, y, z, m, last && coef_last ? coef_last : coef_int, W, w, L, nb,
-                          chunk, s);
+      st = run_coeffs<Rt>(p, n, x, y, z, m, last && coef_last ? coef_last : coef_int, W, w, L, s);
       if (st != SCF_OK) return st;
       // closing half kick of step k merged with the opening half kick of
       // step k+1, then the drift of step k+1

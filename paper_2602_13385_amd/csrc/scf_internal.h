@@ -21,8 +21,10 @@ struct CoefArgs {
   const int64_t* seg_begin;  // per-block particle range [seg_begin[b], seg_end[b])
   const int64_t* seg_end;
   const int32_t* seg_slot;   // per-block output slot (partials row)
-  int64_t begin, chunk, n;   // used when seg_begin == nullptr: block b covers
-                             // [begin + b*chunk, min(begin + (b+1)*chunk, n))
+  int64_t begin, n;          // used when seg_begin == nullptr: the particles
+  int64_t stages;            // [begin, n) form `stages` stages, split evenly: unit u
+                             // takes stages [u*stages/nunits, (u+1)*stages/nunits)
+  int nunits;                // number of wave-units (particle ranges)
   const R* beta_rad;         // [(lmax+1)][(NMAXC+1)]  monic Gegenbauer recurrence
   const R* beta_ang;         // [(lmax+1)][(lmax+1)]   monic Legendre recurrence, [m][l]
   R* partials;               // [nblocks][T]
@@ -69,10 +71,16 @@ struct Engine {
   virtual int lmax() const = 0;
   virtual int dtype() const = 0;
   virtual size_t real_size() const = 0;
-  // number of particles processed per coefficient block-stage
-  virtual int stage_particles() const = 0;
-  // launches the coefficient kernel over nblocks blocks
-  virtual hipError_t launch_coef(const void* args, int nblocks, hipStream_t s) const = 0;
+  // coefficient-kernel variants (basis-phase lanes per particle, waves per block)
+  virtual int coef_variants() const = 0;
+  // particles per wave-stage and waves per block of variant v
+  virtual int stage_particles(int v) const = 0;
+  virtual int waves_per_block(int v) const = 0;
+  // partial-sum rows written per wave-unit, and resident wave-units per CU
+  virtual int rows_per_unit(int v) const = 0;
+  virtual int max_resident_units(int v) const = 0;
+  // launches variant v of the coefficient kernel over nunits wave-units
+  virtual hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const = 0;
   // launches the field kernel; mode 0 = forces, 1 = kick/drift step
   virtual hipError_t launch_force(const void* args, int64_t nblocks, int mode, hipStream_t s) const = 0;
   virtual const char* describe() const = 0;

@@ -34,15 +34,18 @@ constexpr int ntiles_c(int lmax, int jt) {
   return s;
 }
 
-// Tile shape of the accumulation phase, chosen at compile time: the cost
-// model counts VALU issue slots per staged particle plus a penalty for LDS
-// operand words, under a register budget for the accumulators.
-template <typename R, int NMAXC, int LMAX>
+// Tile shape of the accumulation phase, chosen at compile time.  Each lane
+// owns NR rows (n = 0..NMAXC) x JT columns (j) of one degree l and rebuilds the
+// radial column p_n^(l)(xi) itself from two staged numbers (xi and m G_l), so
+// the cost per staged particle is NR*JT FMAs plus 2(NR-2) recurrence ops; the
+// model picks JT (and the number of lane groups G sharing a stage) under a
+// register budget for the accumulators.
+template <typename R, int NMAXC, int LMAX, int LPP_>
 struct CoefShape {
-  static constexpr int LPP = sizeof(R) == 4 ? 2 : 4;
+  static constexpr int LPP = LPP_;
   static constexpr int P = 64 / LPP;
   static constexpr int NR = NMAXC + 1;
-  static constexpr int ACC_MAX = sizeof(R) == 4 ? 96 : 48;
+  static constexpr int ACC_MAX = sizeof(R) == 4 ? 96 : 64;
   struct Pick {
     int jt, g, kt;
   };
@@ -52,16 +55,17 @@ struct CoefShape {
     for (int jt = 1; jt <= 8; ++jt) {
       int nt = ntiles_c(LMAX, jt);
       int kt = ceil_div_c(nt, 64);
-      if (kt * NR * jt > ACC_MAX && !(jt == 1 && kt * NR <= 2 * ACC_MAX)) continue;
+      if (kt * NR * jt > ACC_MAX) continue;
       int g = 1;
       if (kt == 1) {
         g = 64 / nt;
         if (g > P) g = P;
+        if (g > 4) g = 4;
         if (g < 1) g = 1;
       }
       int ppl = ceil_div_c(P, g);
-      double valu = double(kt) * ppl * NR * jt;
-      double lds = double(kt) * ppl * (NR + jt) * (sizeof(R) / 4);
+      double valu = double(kt) * ppl * (NR * jt + 2 * (NR > 2 ? NR - 2 : 0) + 2);
+      double lds = double(kt) * ppl * (jt + 2) * (sizeof(R) / 4);
       double cost = valu + 0.75 * lds;
       if (cost < bcost) {
         bcost = cost;
@@ -73,40 +77,60 @@ struct CoefShape {
   static constexpr Pick pk = pick();
   static constexpr int JT = pk.jt, G = pk.g, KT = pk.kt;
   static constexpr int NT = ntiles_c(LMAX, JT);
+  static constexpr int GS = 64 / G;  // lanes per group: groups start on lane multiples of GS
   static constexpr int L1 = LMAX + 1;
-  static constexpr int NRS = NR;
-  static constexpr int ROFF = L1 * NRS;
-  static constexpr int AL = L1 * L1;
-  static constexpr int PS = (ROFF + AL) | 1;  // odd stride: conflict-free stores
-  static constexpr int TAIL = JT;              // last record's column tiles may overhang
+  // per-particle record: [xi, m G_0 .. m G_LMAX, angular columns tile-padded]
+  static constexpr int GOFF = 1;
+  static constexpr int AOFF = 1 + L1;
+  static constexpr int AL = JT * NT;
+  static constexpr int DUMP = AOFF + AL;          // scratch slot for masked stores
+  static constexpr int PS = (AOFF + AL + 1) | 1;  // odd stride
+  static constexpr int KR = (LMAX + LPP) / LPP;   // orders per lane in the basis phase
+  static constexpr int aoff(int l) { return AOFF + JT * (ntiles_c(l - 1, JT)); }
 };
 
-template <typename R, int NMAXC, int LMAX>
-__global__ void __launch_bounds__(64) coef_kernel(CoefArgs<R> a) {
-  using S = CoefShape<R, NMAXC, LMAX>;
-  constexpr int LPP = S::LPP, P = S::P, NR = S::NR, JT = S::JT, G = S::G, KT = S::KT;
-  constexpr int NT = S::NT, L1 = S::L1, NRS = S::NRS, ROFF = S::ROFF, AL = S::AL, PS = S::PS;
-  static_assert(NT * NR * JT <= P * PS, "group combine must fit the stage buffer");
-  __shared__ R rec[P * PS + S::TAIL];
-  __shared__ R bRad[L1 * NR];
-  __shared__ R bAng[L1 * L1];
+// Wave-local ordering of LDS traffic: every wave works in its own region.
+template <int WPB>
+__device__ __forceinline__ void stage_sync() {
+  if constexpr (WPB == 1) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
 
-  const int lane = threadIdx.x;
-  for (int i = lane; i < L1 * NR; i += 64) bRad[i] = a.beta_rad[i];
-  for (int i = lane; i < L1 * L1; i += 64) bAng[i] = a.beta_ang[i];
-  for (int i = lane; i < P * PS + S::TAIL; i += 64) rec[i] = R(0);
+template <typename R, int NMAXC, int LMAX, int LPP, int WPB>
+__global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
+  using S = CoefShape<R, NMAXC, LMAX, LPP>;
+  constexpr int P = S::P, NR = S::NR, JT = S::JT, G = S::G, KT = S::KT, KR = S::KR;
+  constexpr int NT = S::NT, L1 = S::L1, PS = S::PS, DUMP = S::DUMP;
+  constexpr int REG = P * PS;  // one wave's stage buffer
+  // lane groups are combined through the stage buffer when it is large enough,
+  // otherwise every group writes its own partial row
+  constexpr bool LDS_COMBINE = G == 1 || NT * NR * JT <= P * PS;
+  constexpr int ROWS = LDS_COMBINE ? 1 : G;
+  static_assert(KT > 1 || NT <= S::GS, "a group's tiles must fit its lanes");
+  __shared__ R lds_all[WPB * REG];
 
-  // ---- tile ownership ------------------------------------------------------
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  R* rec = lds_all + wave * REG;
+  for (int i = lane; i < REG; i += 64) rec[i] = R(0);  // padding columns stay zero
+
+  // ---- tile ownership and the owned degrees' recurrence constants ----------
   int grp = 0;
-  int tl[KT], tj[KT];
+  int tl[KT], tj[KT], tt[KT];
   bool tv[KT];
+  R bl[KT][NR];
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     int tau;
     if (KT == 1) {
-      grp = lane / NT;
-      tau = lane % NT;
-      tv[k] = grp < G;
+      grp = lane / S::GS;
+      tau = lane % S::GS;
+      tv[k] = grp < G && tau < NT;
     } else {
       tau = lane + 64 * k;
       tv[k] = tau < NT;
@@ -122,12 +146,11 @@ __global__ void __launch_bounds__(64) coef_kernel(CoefArgs<R> a) {
       rem -= nt;
       l = ll;
     }
-    tl[k] = l;
-    tj[k] = rem * JT;
-    if (!tv[k]) {
-      tl[k] = 0;
-      tj[k] = 0;
-    }
+    tl[k] = tv[k] ? l : 0;
+    tj[k] = tv[k] ? rem * JT : 0;
+    tt[k] = tv[k] ? tau : 0;
+#pragma unroll
+    for (int n = 0; n < NR; ++n) bl[k][n] = a.beta_rad[tl[k] * NR + n];
   }
 
   R acc[KT][NR][JT];
@@ -138,57 +161,54 @@ __global__ void __launch_bounds__(64) coef_kernel(CoefArgs<R> a) {
 #pragma unroll
       for (int j = 0; j < JT; ++j) acc[k][i][j] = R(0);
 
+  // particle range of this wave-unit
+  const int unit = blockIdx.x * WPB + wave;
+  if constexpr (WPB > 1) {
+    if (unit >= a.nunits) return;  // surplus wave of the last block (no block barriers follow)
+  } else {
+    if (unit >= a.nunits) return;
+  }
   int64_t begin, end;
   int slot;
   if (a.seg_begin) {
-    begin = a.seg_begin[blockIdx.x];
-    end = a.seg_end[blockIdx.x];
-    slot = a.seg_slot[blockIdx.x];
+    begin = a.seg_begin[unit];
+    end = a.seg_end[unit];
+    slot = a.seg_slot[unit];
   } else {
-    begin = a.begin + (int64_t)blockIdx.x * a.chunk;
-    end = begin + a.chunk;
+    begin = a.begin + (a.stages * unit / a.nunits) * P;
+    end = a.begin + (a.stages * (unit + 1) / a.nunits) * P;
     if (end > a.n) end = a.n;
-    slot = blockIdx.x;
+    slot = unit;
   }
   const int q = lane / LPP, h = lane % LPP;
   R* rp = rec + q * PS;
-  __syncthreads();
+  stage_sync<WPB>();
 
+  // prefetched particle of the first stage
+  R nx = R(0), ny = R(0), nz = R(0), nm = R(0);
+  {
+    const int64_t gi = begin + q;
+    if (q < P && gi < end) {
+      nx = a.x[gi];
+      ny = a.y[gi];
+      nz = a.z[gi];
+      nm = a.m[gi];
+    }
+  }
   for (int64_t base = begin; base < end; base += P) {
-    // ---- basis phase -------------------------------------------------------
+    // ---- basis phase: xi, m G_l and the angular columns ---------------------
     {
-      const int64_t gi = base + q;
-      const bool valid = gi < end;
-      R x = valid ? a.x[gi] : R(0);
-      R y = valid ? a.y[gi] : R(0);
-      R z = valid ? a.z[gi] : R(0);
-      R mk = valid ? a.m[gi] : R(0);
+      const R x = nx, y = ny, z = nz, mk = nm;
       Geom<R> g = make_geom<R>(x, y, z, a.binv, a.alpha, a.inv_alpha, a.amode);
-      // radial rows: l = h, h + LPP, ...; p_0 = m G_l, p_1 = xi p_0
-      R wl = R(1);
-      for (int t = 0; t < h; ++t) wl *= g.w;
-      R wstep = g.w;
+      if (h == 0) {
+        rp[0] = g.xi;
+        R Gl = mk * g.g0;
 #pragma unroll
-      for (int t = 1; t < LPP; ++t) wstep *= g.w;
-      R Gl = mk * g.g0 * wl;
-#pragma unroll
-      for (int kk = 0; kk * LPP <= LMAX; ++kk) {
-        const int l = h + kk * LPP;
-        if (l <= LMAX) {
-          R p0 = Gl, p1 = g.xi * Gl;
-          rp[l * NRS + 0] = p0;
-          if constexpr (NMAXC >= 1) rp[l * NRS + 1] = p1;
-#pragma unroll
-          for (int nn = 2; nn <= NMAXC; ++nn) {
-            R p2 = g.xi * p1 - bRad[l * NR + nn] * p0;
-            rp[l * NRS + nn] = p2;
-            p0 = p1;
-            p1 = p2;
-          }
+        for (int l = 0; l <= LMAX; ++l) {
+          rp[S::GOFF + l] = Gl;
+          Gl *= g.w;
         }
-        Gl *= wstep;
       }
-      // angular columns: m = h, h + LPP, ...
       R er = R(1), ei = R(0);
       for (int t = 0; t < h; ++t) {
         R nr = er * g.ux - ei * g.uy;
@@ -203,84 +223,111 @@ __global__ void __launch_bounds__(64) coef_kernel(CoefArgs<R> a) {
         sr = nr;
       }
 #pragma unroll
-      for (int kk = 0; kk * LPP <= LMAX; ++kk) {
+      for (int kk = 0; kk < KR; ++kk) {
         const int mm = h + kk * LPP;
+        const bool mv = mm <= LMAX;
+        const int mc = mv ? mm : LMAX;
+        const int offc = mm > 0 ? 2 * mm - 1 : 0;
+        const int offs = 2 * mm;
+        const R m2 = R(mc) * R(mc);
         R Q0 = R(0), Q1 = R(0);
 #pragma unroll
         for (int l = kk * LPP; l <= LMAX; ++l) {
-          if (mm <= LMAX && l >= mm) {
-            R Q;
-            if (l == mm) Q = R(1);
-            else if (l == mm + 1) Q = g.c;
-            else Q = g.c * Q1 - bAng[mm * L1 + l] * Q0;
-            Q0 = Q1;
-            Q1 = Q;
-            if (mm == 0) {
-              rp[ROFF + l * l] = Q;
-            } else {
-              rp[ROFF + l * l + 2 * mm - 1] = Q * er;
-              rp[ROFF + l * l + 2 * mm] = Q * ei;
-            }
-          }
+          // gamma_lm = ((l-1)^2 - m^2) / ((2l-1)(2l-3)), used for l >= m+2
+          const R cl = l >= 2 ? R(1) / R((2 * l - 1) * (2 * l - 3)) : R(0);
+          const R gam = fma(-m2, cl, R((l - 1) * (l - 1)) * cl);
+          const R qg = g.c * Q1 - gam * Q0;
+          const R Q = (l == mm) ? R(1) : qg;
+          Q0 = Q1;
+          Q1 = Q;
+          const bool ok = mv && l >= mm;
+          const int ic = ok ? S::aoff(l) + offc : DUMP;
+          const int is = (ok && mm > 0) ? S::aoff(l) + offs : DUMP;
+          rp[is] = Q * ei;
+          rp[ic] = Q * er;
         }
         R nr = er * sr - ei * si;
         ei = er * si + ei * sr;
         er = nr;
       }
     }
-    __syncthreads();
+    stage_sync<WPB>();
+    // prefetch the next stage's particle while accumulating
+    {
+      const int64_t gi = base + P + q;
+      if (gi < end) {
+        nx = a.x[gi];
+        ny = a.y[gi];
+        nz = a.z[gi];
+        nm = a.m[gi];
+      } else {
+        nx = ny = nz = nm = R(0);
+      }
+    }
     // ---- accumulation phase ------------------------------------------------
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
       if (tv[k]) {
-        const R* rb = rec + tl[k] * NRS;
-        const R* ab = rec + ROFF + tl[k] * tl[k] + tj[k];
+        const R* gb = rec + S::GOFF + tl[k];
+        const R* ab = rec + S::AOFF + JT * tt[k];
         constexpr int PPL = (P + G - 1) / G;
 #pragma unroll 2
         for (int ii = 0; ii < PPL; ++ii) {
           const int p = grp + G * ii;
           if (G * PPL == P || p < P) {
-            R rv[NR], av[JT];
-#pragma unroll
-            for (int i = 0; i < NR; ++i) rv[i] = rb[p * PS + i];
+            const R xi = rec[p * PS];
+            R p0 = gb[p * PS];
+            R av[JT];
 #pragma unroll
             for (int j = 0; j < JT; ++j) av[j] = ab[p * PS + j];
 #pragma unroll
-            for (int i = 0; i < NR; ++i)
+            for (int j = 0; j < JT; ++j) acc[k][0][j] = fma(p0, av[j], acc[k][0][j]);
+            if constexpr (NR > 1) {
+              R p1 = xi * p0;
 #pragma unroll
-              for (int j = 0; j < JT; ++j) acc[k][i][j] = fma(rv[i], av[j], acc[k][i][j]);
+              for (int j = 0; j < JT; ++j) acc[k][1][j] = fma(p1, av[j], acc[k][1][j]);
+#pragma unroll
+              for (int i = 2; i < NR; ++i) {
+                const R p2 = fma(xi, p1, -bl[k][i] * p0);
+#pragma unroll
+                for (int j = 0; j < JT; ++j) acc[k][i][j] = fma(p2, av[j], acc[k][i][j]);
+                p0 = p1;
+                p1 = p2;
+              }
+            }
           }
         }
       }
     }
-    __syncthreads();
+    stage_sync<WPB>();
   }
 
-  // ---- combine lane groups (in rounds) and write this block's partials -------
-  if constexpr (G > 1) {
+  // ---- combine lane groups (in rounds) and write this unit's partials -------
+  if constexpr (G > 1 && LDS_COMBINE) {
     for (int gg = 1; gg < G; ++gg) {
       if (grp == gg && tv[0]) {
-        R* dst = rec + (lane % NT) * NR * JT;
+        R* dst = rec + tt[0] * NR * JT;
 #pragma unroll
         for (int i = 0; i < NR; ++i)
 #pragma unroll
           for (int j = 0; j < JT; ++j) dst[i * JT + j] = acc[0][i][j];
       }
-      __syncthreads();
+      stage_sync<WPB>();
       if (grp == 0 && tv[0]) {
-        const R* src = rec + lane * NR * JT;
+        const R* src = rec + tt[0] * NR * JT;
 #pragma unroll
         for (int i = 0; i < NR; ++i)
 #pragma unroll
           for (int j = 0; j < JT; ++j) acc[0][i][j] += src[i * JT + j];
       }
-      __syncthreads();
+      stage_sync<WPB>();
     }
   }
-  R* out = a.partials + (int64_t)slot * a.T;
+  R* out = a.partials + ((int64_t)slot * ROWS + (LDS_COMBINE ? 0 : grp)) * a.T;
+  constexpr int AL2 = L1 * L1;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    if (tv[k] && grp == 0) {
+    if (tv[k] && (grp == 0 || !LDS_COMBINE)) {
       const int l = tl[k];
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
@@ -288,7 +335,7 @@ __global__ void __launch_bounds__(64) coef_kernel(CoefArgs<R> a) {
 #pragma unroll
           for (int j = 0; j < JT; ++j) {
             const int jj = tj[k] + j;
-            if (jj <= 2 * l) out[i * AL + l * l + jj] = acc[k][i][j];
+            if (jj <= 2 * l) out[i * AL2 + l * l + jj] = acc[k][i][j];
           }
         }
       }
@@ -626,17 +673,65 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // engines
 // ---------------------------------------------------------------------------
+template <typename R>
+struct CoefVariants;
+template <>
+struct CoefVariants<float> {
+  static constexpr int N = 3;
+  static constexpr int LPP[N] = {2, 1, 4};
+  static constexpr int WPB[N] = {1, 1, 1};
+};
+template <>
+struct CoefVariants<double> {
+  static constexpr int N = 3;
+  static constexpr int LPP[N] = {4, 2, 8};
+  static constexpr int WPB[N] = {1, 1, 1};
+};
+
 template <typename R, int NMAXC, int LMAX>
 struct EngineImpl final : Engine {
-  using S = CoefShape<R, NMAXC, LMAX>;
+  using V = CoefVariants<R>;
   int nmaxc() const override { return NMAXC; }
   int lmax() const override { return LMAX; }
   int dtype() const override { return sizeof(R) == 4 ? 0 : 1; }
   size_t real_size() const override { return sizeof(R); }
-  int stage_particles() const override { return S::P; }
-  hipError_t launch_coef(const void* args, int nblocks, hipStream_t s) const override {
-    if (nblocks <= 0) return hipSuccess;
-    coef_kernel<R, NMAXC, LMAX><<<nblocks, 64, 0, s>>>(*(const CoefArgs<R>*)args);
+  int coef_variants() const override { return V::N; }
+  int stage_particles(int v) const override { return 64 / V::LPP[v]; }
+  int rows_per_unit(int v) const override {
+    return v == 0 ? rows_t<V::LPP[0]>() : v == 1 ? rows_t<V::LPP[1]>() : rows_t<V::LPP[2]>();
+  }
+  template <int LPP>
+  static constexpr int rows_t() {
+    using S = CoefShape<R, NMAXC, LMAX, LPP>;
+    return (S::G == 1 || S::NT * S::NR * S::JT <= S::P * S::PS) ? 1 : S::G;
+  }
+  int max_resident_units(int v) const override {
+    int per_cu = 0;
+    hipError_t e;
+    if (v == 0)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[0], V::WPB[0]>, 64 * V::WPB[0], 0);
+    else if (v == 1)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[1], V::WPB[1]>, 64 * V::WPB[1], 0);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[2], V::WPB[2]>, 64 * V::WPB[2], 0);
+    if (e != hipSuccess || per_cu <= 0) per_cu = 1;
+    return per_cu * V::WPB[v];
+  }
+  int waves_per_block(int v) const override { return V::WPB[v]; }
+  hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const override {
+    if (nunits <= 0) return hipSuccess;
+    const CoefArgs<R>& ca = *(const CoefArgs<R>*)args;
+    const int wpb = V::WPB[v];
+    const int nblocks = (nunits + wpb - 1) / wpb;
+    if (v == 0)
+      coef_kernel<R, NMAXC, LMAX, V::LPP[0], V::WPB[0]><<<nblocks, 64 * V::WPB[0], 0, s>>>(ca);
+    else if (v == 1)
+      coef_kernel<R, NMAXC, LMAX, V::LPP[1], V::WPB[1]><<<nblocks, 64 * V::WPB[1], 0, s>>>(ca);
+    else
+      coef_kernel<R, NMAXC, LMAX, V::LPP[2], V::WPB[2]><<<nblocks, 64 * V::WPB[2], 0, s>>>(ca);
     return hipGetLastError();
   }
   hipError_t launch_force(const void* args, int64_t nblocks, int mode,
@@ -652,9 +747,13 @@ struct EngineImpl final : Engine {
     return hipGetLastError();
   }
   const char* describe() const override {
-    static char buf[160];
-    snprintf(buf, sizeof(buf), "%s nmax<=%d lmax=%d coef tile %dx%d groups=%d tiles/lane=%d",
-             sizeof(R) == 4 ? "f32" : "f64", NMAXC, LMAX, S::NR, S::JT, S::G, S::KT);
+    static char buf[200];
+    using S0 = CoefShape<R, NMAXC, LMAX, V::LPP[0]>;
+    using S2 = CoefShape<R, NMAXC, LMAX, V::LPP[2]>;
+    snprintf(buf, sizeof(buf),
+             "%s nmax<=%d lmax=%d coef tiles %dx%d (groups %d|%d, tiles/lane %d|%d)",
+             sizeof(R) == 4 ? "f32" : "f64", NMAXC, LMAX, S0::NR, S0::JT, S0::G, S2::G, S0::KT,
+             S2::KT);
     return buf;
   }
 };

@@ -75,6 +75,11 @@ SIGNATURES = {
                                    C.POINTER(CHost), _dp, C.c_double, C.c_int32, C.POINTER(_vp),
                                    _dp, _dp, _vp, C.c_size_t, _vp]),
     "scf_adjoint_workspace_size": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scf_plan_num_variants": (C.c_int32, [_vp]),
+    "scf_plan_variant": (C.c_int32, [_vp]),
+    "scf_plan_set_variant": (C.c_int, [_vp, C.c_int32]),
+    "scf_plan_describe": (C.c_char_p, [_vp]),
+    "scf_autotune": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _dp]),
     "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
     "scf_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -161,6 +166,30 @@ class Plan:
         if h and h.value and _lib is not None:
             _lib.scf_plan_destroy(h)
             self._h = None
+
+    @property
+    def num_variants(self):
+        return int(lib().scf_plan_num_variants(self._h))
+
+    @property
+    def variant(self):
+        return int(lib().scf_plan_variant(self._h))
+
+    @variant.setter
+    def variant(self, v):
+        _check(lib().scf_plan_set_variant(self._h, int(v)))
+
+    def describe(self):
+        return lib().scf_plan_describe(self._h).decode()
+
+    def autotune(self, x, y, z, m):
+        """Time the coefficient-kernel variants on these particles; keep the fastest."""
+        self._check_arrays(x, y, z, m)
+        ws = self.workspace(x.numel(), device=x.device)
+        best = C.c_double(0.0)
+        _check(lib().scf_autotune(self._h, x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(m), _ptr(ws),
+                                  ws.numel(), _stream(), C.byref(best)))
+        return self.variant, best.value
 
     def profile(self, enable=True):
         """Turn per-kernel HIP-event timing on or off."""

@@ -88,8 +88,10 @@ def test_coeffs_and_forces_match_oracle(torch, S, O, case, dtype):
     B = O.basis(nmax, lmax, alpha=alpha)
     ref = O.coeffs(B, *pos, m)
     plan = S.Plan(nmax, lmax, alpha=alpha, dtype=dtype)
-    c = _gpu_coeffs(torch, S, plan, pos, m, dtype)
-    assert coef_err(c, ref) <= TOL[dtype], coef_err(c, ref)
+    for v in range(plan.num_variants):
+        plan.variant = v
+        c = _gpu_coeffs(torch, S, plan, pos, m, dtype)
+        assert coef_err(c, ref) <= TOL[dtype], (v, coef_err(c, ref))
     # forces from the reference coefficients, at a sample of the particles
     k = min(n, 2000)
     sub = pos[:, :k]
@@ -143,8 +145,10 @@ def test_edge_cases(torch, S, O, dtype):
     m = np.array([0.2, 0.3, 0.1, 0.25, 0.15])
     for k in (1, 5):
         ref = O.coeffs(B, *pos[:, :k], m[:k])
-        cg = _gpu_coeffs(torch, S, plan, _rounded(pos[:, :k], dtype), _rounded(m[:k], dtype), dtype)
-        assert coef_err(cg, ref) <= TOL[dtype]
+        for v in range(plan.num_variants):
+            plan.variant = v
+            cg = _gpu_coeffs(torch, S, plan, _rounded(pos[:, :k], dtype), _rounded(m[:k], dtype), dtype)
+            assert coef_err(cg, ref) <= TOL[dtype]
     ref = O.coeffs(B, *pos, m)
     _, gref = O.field(B, ref, *pos)
     x, y, z = (_dev(torch, pos[i], dtype) for i in range(3))
@@ -160,9 +164,22 @@ def test_coefficients_are_deterministic(torch, S):
     p = I.plummer(50_000, 5)
     plan = S.Plan(10, 6)
     x, y, z, m = (_dev(torch, a, "f32") for a in (*p.pos, p.mass))
-    c1 = plan.coeffs(x, y, z, m).cpu().numpy()
-    c2 = plan.coeffs(x, y, z, m).cpu().numpy()
-    assert np.array_equal(c1, c2)
+    for v in range(plan.num_variants):
+        plan.variant = v
+        c1 = plan.coeffs(x, y, z, m).cpu().numpy()
+        c2 = plan.coeffs(x, y, z, m).cpu().numpy()
+        assert np.array_equal(c1, c2)
+
+
+def test_autotune_picks_a_valid_variant(torch, S, O):
+    p = I.plummer(40_000, 6)
+    plan = S.Plan(10, 6)
+    x, y, z, m = (_dev(torch, a, "f32") for a in (*p.pos, p.mass))
+    v, ms = plan.autotune(x, y, z, m)
+    assert 0 <= v < plan.num_variants and ms > 0
+    ref = O.coeffs(O.basis(10, 6), *_rounded(p.pos, "f32"), _rounded(p.mass, "f32"))
+    c = plan.coeffs(x, y, z, m).cpu().numpy()
+    assert coef_err(c, ref) <= TOL["f32"]
 
 
 def test_hernquist_quadrature_closed_form(torch, S):
