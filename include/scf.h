@@ -100,6 +100,7 @@ typedef struct scf_plan scf_plan;
 
 /* scf_step flags */
 #define SCF_STEP_ACC_VALID 1u /* ax, ay, az already hold a(x) at entry */
+#define SCF_STEP_NO_GRAPH 2u  /* scf_step_batched: launch the kernels directly, no HIP graph */
 
 /* (nmax+1)(lmax+1)^2, or 0 for negative arguments. */
 int64_t scf_ncoef(int32_t nmax, int32_t lmax);
@@ -144,12 +145,24 @@ scf_status scf_step(scf_plan* plan, int64_t n, void* x, void* y, void* z, void* 
                     double* coef_last, void* ws, size_t ws_bytes, void* stream);
 
 /* scf_step for nclusters independent clusters concatenated in the particle
- * arrays: cluster c owns particles [offsets[c], offsets[c+1]) (host array,
- * offsets[0] = 0, non-decreasing).  Each cluster has its own coefficients and
- * frame centre (centres: host, nclusters*6, in/out); all share the host
- * potential.  The step's kernels are launched once for all clusters through
- * a static work list, captured in a HIP graph and replayed every step.
- * coef_last (device, nullable) receives nclusters*ncoef doubles. */
+ * arrays: cluster c owns particles [offsets[c], offsets[c+1]) (host array of
+ * nclusters+1 entries, offsets[0] = 0, non-decreasing; n = offsets[nclusters]).
+ * Each cluster has its own coefficients (Eq. sumanlm over its own particles)
+ * and frame centre (centres: host, nclusters*6 = R, V per cluster, in/out,
+ * advanced in double precision on the host); all share the host potential.
+ * One step is one launch each of the coefficient, reduction, finalisation and
+ * field kernels for all clusters together, driven by static work lists (a
+ * cluster's particle ranges per wave-unit, its partial rows, its 256-particle
+ * field blocks) built on the host per call.  The middle steps (all but the
+ * last) are captured once into a HIP graph (on a plan-owned stream; recaptured
+ * when pointers, sizes, dt or the host change) and replayed on stream; with
+ * SCF_STEP_NO_GRAPH the same kernels are launched directly, with bitwise
+ * identical results.  The per-step centre rows are uploaded in chunks of 256
+ * steps and selected on the device.  The workspace must come from
+ * scf_workspace_size(plan, n, nclusters).  step_flags and the returned state
+ * are as for scf_step; coef_last (device, nullable) receives nclusters*ncoef
+ * doubles, cluster-major.  A plan must not run two batched calls
+ * concurrently (the graph and the pinned staging buffers are per plan). */
 scf_status scf_step_batched(scf_plan* plan, int32_t nclusters, const int64_t* offsets, void* x,
                             void* y, void* z, void* vx, void* vy, void* vz, const void* m,
                             void* ax, void* ay, void* az, uint32_t step_flags, const scf_host* host,
@@ -181,6 +194,8 @@ scf_status scf_adjoint_workspace_size(const scf_plan* plan, int64_t n, int32_t n
  * Variants give results that agree to rounding (the particle sums are grouped
  * differently); a fixed variant is bitwise reproducible. */
 int32_t scf_plan_num_variants(const scf_plan* plan);
+/* Number of HIP graphs the plan has captured for scf_step_batched so far. */
+int32_t scf_plan_graph_captures(const scf_plan* plan);
 int32_t scf_plan_variant(const scf_plan* plan);
 scf_status scf_plan_set_variant(scf_plan* plan, int32_t variant);
 const char* scf_plan_describe(const scf_plan* plan);

@@ -192,6 +192,19 @@ struct scf_plan {
     hipEvent_t a, b;
   };
   std::vector<Rec> recs;
+  // batched mode: the captured per-step graph, the stream it is captured on,
+  // and pinned host staging for the work list and the centre table
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<char> gkey;
+  int graph_captures = 0;
+  double* h_tab = nullptr;
+  size_t h_tab_cap = 0;
+  char* h_meta = nullptr;
+  size_t h_meta_cap = 0;
+  hipEvent_t ev_staging = nullptr;
+  bool staging_pending = false;
 };
 
 namespace {
@@ -200,7 +213,7 @@ enum Kind { K_COEF = 0, K_REDUCE, K_FINALIZE, K_FIELD, K_STEP_FIELD, K_KICK, K_M
             K_BATCH_COEF, K_BATCH_FIELD, K_ADJ, K_OTHER };
 const char* kKindNames[SCF_KERNEL_KINDS] = {"coef", "reduce", "finalize", "field", "field_step",
                                             "kick_drift", "make_w", "fill", "batched_coef",
-                                            "batched_field", "adjoint", "other"};
+                                            "batched_step", "adjoint", "other"};
 
 // brackets one launch with events when the plan's timing is on
 struct Timed {
@@ -209,7 +222,7 @@ struct Timed {
   int kind;
   hipEvent_t b = nullptr;
   Timed(scf_plan* p_, hipStream_t s_, int k) : p(p_), s(s_), kind(k) {
-    if (p && p->prof && p->ev_next + 2 <= p->ev_pool.size()) {
+    if (p && p->prof && p->ev_next + 2 <= p->ev_pool.size() && s != p->cap_stream) {
       hipEvent_t a = p->ev_pool[p->ev_next++];
       b = p->ev_pool[p->ev_next++];
       (void)hipEventRecord(a, s);
@@ -276,6 +289,55 @@ WsLayout ws_layout(const scf_plan* p, int64_t n, int nclusters, int nblocks) {
   L.total = off;
   (void)n;
   return L;
+}
+
+size_t plain_need(const scf_plan* p, int64_t n) { return ws_layout(p, n, 1, 0).total; }
+
+// Batched workspace: the common layout for nclusters, then the centre-table
+// chunk, the current centre rows and step counter, and the work lists.
+constexpr int kCentreRows = 256;  // centre-table rows uploaded per chunk
+
+struct BatchLayout {
+  WsLayout L;
+  size_t tab, cur, ctr, seg_begin, seg_end, seg_slot, rows, blk_cluster, blk_begin, blk_end, total;
+  int max_units;
+  int64_t max_blocks;
+};
+
+BatchLayout batch_layout(const scf_plan* p, int64_t n, int ncl) {
+  BatchLayout B;
+  int max_units = 0, max_rows = 0;
+  for (int v = 0; v < p->eng->coef_variants(); ++v) {
+    const int u = p->resident[v] * p->num_cu + ncl;
+    max_units = std::max(max_units, u);
+    max_rows = std::max(max_rows, u * p->eng->rows_per_unit(v));
+  }
+  B.max_units = max_units;
+  B.max_blocks = (n + 255) / 256 + ncl;
+  B.L = ws_layout(p, n, ncl, max_rows);
+  size_t off = B.L.total;
+  B.tab = off;
+  off += align256((size_t)kCentreRows * ncl * 9 * sizeof(double));
+  B.cur = off;
+  off += align256((size_t)ncl * 9 * sizeof(double));
+  B.ctr = off;
+  off += 256;
+  B.seg_begin = off;
+  off += align256((size_t)max_units * 8);
+  B.seg_end = off;
+  off += align256((size_t)max_units * 8);
+  B.seg_slot = off;
+  off += align256((size_t)max_units * 4);
+  B.rows = off;
+  off += align256((size_t)(ncl + 1) * 4);
+  B.blk_cluster = off;
+  off += align256((size_t)B.max_blocks * 4);
+  B.blk_begin = off;
+  off += align256((size_t)B.max_blocks * 8);
+  B.blk_end = off;
+  off += align256((size_t)B.max_blocks * 8);
+  B.total = off;
+  return B;
 }
 
 template <typename R>
@@ -471,8 +533,7 @@ scf_status scf_autotune(scf_plan* p, int64_t n, const void* x, const void* y, co
   if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
   if (n <= 0) return SCF_OK;
   if (!(x && y && z && m)) return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
-  size_t need;
-  scf_workspace_size(p, n, 1, &need);
+  const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
   hipStream_t s = (hipStream_t)stream;
@@ -626,6 +687,15 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
 void scf_plan_destroy(scf_plan* p) {
   if (!p) return;
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->ev_staging) {
+    (void)hipEventSynchronize(p->ev_staging);
+    (void)hipEventDestroy(p->ev_staging);
+  }
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->h_tab) (void)hipHostFree(p->h_tab);
+  if (p->h_meta) (void)hipHostFree(p->h_meta);
   if (p->d_beta_rad) (void)hipFree(p->d_beta_rad);
   if (p->d_beta_ang) (void)hipFree(p->d_beta_ang);
   if (p->d_cs) (void)hipFree(p->d_cs);
@@ -636,10 +706,8 @@ void scf_plan_destroy(scf_plan* p) {
 scf_status scf_workspace_size(const scf_plan* p, int64_t n, int32_t nclusters, size_t* bytes) {
   if (!p || !bytes) return fail(SCF_ERR_INVALID_ARG, "plan and bytes must be non-null");
   if (n < 0 || nclusters < 1) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nclusters >= 1");
-  int nb = coef_blocks_max(p, n);
-  nb += nclusters;  // batched mode: one extra partial block per cluster boundary
-  *bytes = ws_layout(p, n, nclusters, nb).total + align256((size_t)nclusters * 64 * sizeof(double)) +
-           align256((size_t)(nb + 2 * ((n + 255) / 256 + nclusters)) * 3 * sizeof(int64_t));
+  if (nclusters > (1 << 20)) return fail(SCF_ERR_INVALID_ARG, "nclusters = %d too large", nclusters);
+  *bytes = std::max(plain_need(p, n), batch_layout(p, n, nclusters).total);
   return SCF_OK;
 }
 
@@ -650,8 +718,7 @@ scf_status scf_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
   if (!coef) return fail(SCF_ERR_INVALID_ARG, "coef is null");
   if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(m)))
     return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
-  size_t need;
-  scf_workspace_size(p, n, 1, &need);
+  const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
   const WsLayout L = ws_layout(p, n, 1, 0);
@@ -674,8 +741,7 @@ scf_status scf_forces(scf_plan* p, int64_t n, const void* x, const void* y, cons
   if (hs != SCF_OK) return hs;
   const bool with_host = host && host->ncomp > 0;
   if (with_host && !centre) return fail(SCF_ERR_INVALID_ARG, "centre is null with a host potential");
-  size_t need;
-  scf_workspace_size(p, n, 1, &need);
+  const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
   const WsLayout L = ws_layout(p, n, 1, 0);
@@ -722,8 +788,7 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
     return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
   scf_status hs = check_host(host);
   if (hs != SCF_OK) return hs;
-  size_t need;
-  scf_workspace_size(p, n, 1, &need);
+  const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
   const WsLayout L = ws_layout(p, n, 1, 0);
@@ -800,11 +865,304 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
                             void* ay, void* az, uint32_t step_flags, const scf_host* host,
                             double* centres, double dt, int32_t nsteps, double* coef_last, void* ws,
                             size_t ws_bytes, void* stream) {
-  (void)p; (void)nclusters; (void)offsets; (void)x; (void)y; (void)z; (void)vx; (void)vy; (void)vz;
-  (void)m; (void)ax; (void)ay; (void)az; (void)step_flags; (void)host; (void)centres; (void)dt;
-  (void)nsteps; (void)coef_last; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(SCF_ERR_UNSUPPORTED, "scf_step_batched: not built yet");
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (nclusters < 1 || nsteps < 0) return fail(SCF_ERR_INVALID_ARG, "need nclusters >= 1 and nsteps >= 0");
+  if (!offsets || !centres) return fail(SCF_ERR_INVALID_ARG, "offsets and centres must be non-null");
+  if (!std::isfinite(dt)) return fail(SCF_ERR_INVALID_ARG, "dt is not finite");
+  if (step_flags & ~(SCF_STEP_ACC_VALID | SCF_STEP_NO_GRAPH))
+    return fail(SCF_ERR_INVALID_ARG, "unknown step flags");
+  if (offsets[0] != 0) return fail(SCF_ERR_INVALID_ARG, "offsets[0] must be 0");
+  for (int c = 0; c < nclusters; ++c)
+    if (offsets[c + 1] < offsets[c])
+      return fail(SCF_ERR_INVALID_ARG, "offsets must be non-decreasing (cluster %d)", c);
+  const int64_t n = offsets[nclusters];
+  if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(vx) && ptr_ok(vy) && ptr_ok(vz) &&
+                 ptr_ok(m) && ptr_ok(ax) && ptr_ok(ay) && ptr_ok(az)))
+    return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
+  scf_status hs = check_host(host);
+  if (hs != SCF_OK) return hs;
+  const int ncl = nclusters;
+  const BatchLayout B = batch_layout(p, n, ncl);
+  if (!ws || ws_bytes < B.total)
+    return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", B.total, ws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const bool with_host = host && host->ncomp > 0;
+  HostParams<double> hd;
+  fill_host_params(hd, with_host ? host : nullptr);
+  const bool acc_valid = (step_flags & SCF_STEP_ACC_VALID) && nsteps > 0;
+  const bool use_graph = !(step_flags & SCF_STEP_NO_GRAPH);
+
+  // ---- work lists (host), staged in pinned memory --------------------------
+  const int v = p->coef_variant;
+  const int P = p->eng->stage_particles(v);
+  const int rpu = p->eng->rows_per_unit(v);
+  const int cap = std::max(1, p->resident[v] * p->num_cu);
+  std::vector<int64_t> stg(ncl);
+  int64_t st_tot = 0;
+  for (int c = 0; c < ncl; ++c) {
+    stg[c] = (offsets[c + 1] - offsets[c] + P - 1) / P;
+    st_tot += stg[c];
+  }
+  std::vector<int64_t> sb, se;
+  std::vector<int32_t> slot, rows(ncl + 1, 0), bcl;
+  std::vector<int64_t> bb, be;
+  for (int c = 0; c < ncl; ++c) {
+    rows[c] = (int32_t)(sb.size() * rpu);
+    if (stg[c] == 0) continue;
+    int64_t uc = (int64_t)((double)cap * (double)stg[c] / (double)st_tot);
+    uc = std::max<int64_t>(1, std::min<int64_t>(uc, stg[c]));
+    for (int64_t u = 0; u < uc; ++u) {
+      const int64_t s0 = stg[c] * u / uc, s1 = stg[c] * (u + 1) / uc;
+      sb.push_back(offsets[c] + s0 * P);
+      se.push_back(std::min(offsets[c] + s1 * P, offsets[c + 1]));
+      slot.push_back((int32_t)slot.size());
+    }
+  }
+  rows[ncl] = (int32_t)(sb.size() * rpu);
+  for (int c = 0; c < ncl; ++c)
+    for (int64_t b0 = offsets[c]; b0 < offsets[c + 1]; b0 += 256) {
+      bcl.push_back(c);
+      bb.push_back(b0);
+      be.push_back(std::min(b0 + 256, offsets[c + 1]));
+    }
+  const int U = (int)sb.size();
+  const int64_t nblk = (int64_t)bcl.size();
+  if (U > B.max_units || nblk > B.max_blocks)
+    return fail(SCF_ERR_INVALID_ARG, "internal: work list larger than its workspace");
+
+  // ---- centre orbit (host, double): rows k = 0..nsteps of R, grad psi_host(R)
+  const int64_t nrows = (int64_t)nsteps + 1;
+  const size_t tab_elems = (size_t)nrows * ncl * 9;
+  const size_t meta_bytes = (size_t)U * 20 + (size_t)(ncl + 1) * 4 + (size_t)nblk * 20;
+  if (p->staging_pending) {
+    HIP_TRY(hipEventSynchronize(p->ev_staging));
+    p->staging_pending = false;
+  }
+  if (p->h_tab_cap < tab_elems) {
+    if (p->h_tab) HIP_TRY(hipHostFree(p->h_tab));
+    p->h_tab = nullptr;
+    p->h_tab_cap = 0;
+    HIP_TRY(hipHostMalloc((void**)&p->h_tab, tab_elems * sizeof(double), hipHostMallocDefault));
+    p->h_tab_cap = tab_elems;
+  }
+  if (p->h_meta_cap < meta_bytes) {
+    if (p->h_meta) HIP_TRY(hipHostFree(p->h_meta));
+    p->h_meta = nullptr;
+    p->h_meta_cap = 0;
+    HIP_TRY(hipHostMalloc((void**)&p->h_meta, meta_bytes, hipHostMallocDefault));
+    p->h_meta_cap = meta_bytes;
+  }
+  if (!p->ev_staging) HIP_TRY(hipEventCreateWithFlags(&p->ev_staging, hipEventDisableTiming));
+  const double h = 0.5 * dt;
+  std::vector<double> cnew(6 * (size_t)ncl);
+  for (int c = 0; c < ncl; ++c) {
+    double R[3] = {centres[6 * c], centres[6 * c + 1], centres[6 * c + 2]};
+    double V[3] = {centres[6 * c + 3], centres[6 * c + 4], centres[6 * c + 5]};
+    auto put_row = [&](int64_t k) {
+      double g[3] = {0, 0, 0};
+      if (with_host) host_grad<double>(hd, R[0], R[1], R[2], g[0], g[1], g[2]);
+      double* row = p->h_tab + ((size_t)k * ncl + c) * 9;
+      for (int i = 0; i < 3; ++i) {
+        row[i] = R[i];
+        row[3 + i] = g[i];
+        row[6 + i] = 0.0;
+      }
+    };
+    put_row(0);
+    if (nsteps > 0) {
+      double gc[3];
+      centre_accel(hd, R, gc);
+      for (int i = 0; i < 3; ++i) V[i] += h * gc[i];
+      for (int i = 0; i < 3; ++i) R[i] += dt * V[i];
+      for (int k = 1; k <= nsteps; ++k) {
+        const bool last = k == nsteps;
+        put_row(k);
+        centre_accel(hd, R, gc);
+        for (int i = 0; i < 3; ++i) V[i] += (last ? h : dt) * gc[i];
+        if (!last)
+          for (int i = 0; i < 3; ++i) R[i] += dt * V[i];
+      }
+    }
+    for (int i = 0; i < 3; ++i) {
+      cnew[6 * c + i] = R[i];
+      cnew[6 * c + 3 + i] = V[i];
+    }
+  }
+  {
+    char* q = p->h_meta;
+    auto put = [&](const void* src, size_t bytes) {
+      if (bytes) std::memcpy(q, src, bytes);
+      q += bytes;
+    };
+    put(sb.data(), (size_t)U * 8);
+    put(se.data(), (size_t)U * 8);
+    put(slot.data(), (size_t)U * 4);
+    put(rows.data(), (size_t)(ncl + 1) * 4);
+    put(bcl.data(), (size_t)nblk * 4);
+    put(bb.data(), (size_t)nblk * 8);
+    put(be.data(), (size_t)nblk * 8);
+    const char* q0 = p->h_meta;
+    size_t o = 0;
+    auto up = [&](size_t dst, size_t bytes) -> hipError_t {
+      hipError_t e = bytes ? hipMemcpyAsync(w + dst, q0 + o, bytes, hipMemcpyHostToDevice, s)
+                           : hipSuccess;
+      o += bytes;
+      return e;
+    };
+    HIP_TRY(up(B.seg_begin, (size_t)U * 8));
+    HIP_TRY(up(B.seg_end, (size_t)U * 8));
+    HIP_TRY(up(B.seg_slot, (size_t)U * 4));
+    HIP_TRY(up(B.rows, (size_t)(ncl + 1) * 4));
+    HIP_TRY(up(B.blk_cluster, (size_t)nblk * 4));
+    HIP_TRY(up(B.blk_begin, (size_t)nblk * 8));
+    HIP_TRY(up(B.blk_end, (size_t)nblk * 8));
+  }
+  // uploads rows [k0, k0 + kCentreRows) of the centre table and restarts the
+  // device row counter
+  auto upload_rows = [&](int64_t k0) -> scf_status {
+    const int64_t k1 = std::min<int64_t>(k0 + kCentreRows, nrows);
+    HIP_TRY(hipMemcpyAsync(w + B.tab, p->h_tab + (size_t)k0 * ncl * 9,
+                           (size_t)(k1 - k0) * ncl * 9 * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_set_int((int*)(w + B.ctr), 0, s));
+    return SCF_OK;
+  };
+
+  const int nch = std::max(1, std::min(kReduceChunks, rows[ncl] > 0 ? (rows[ncl] + ncl - 1) / ncl : 1));
+  const int64_t W_stride = (int64_t)(p->nmaxc + 1) * (p->lmax + 1) * (p->lmax + 1);
+  double* coef_int = (double*)(w + B.L.coef);
+  void* Wb = w + B.L.W;
+
+  auto go = [&](auto tag) -> scf_status {
+    using Rt = decltype(tag);
+    HostParams<Rt> hp;
+    fill_host_params(hp, with_host ? host : nullptr);
+    CoefArgs<Rt> ca;
+    fill_coef_common(ca, p);
+    ca.x = (const Rt*)x;
+    ca.y = (const Rt*)y;
+    ca.z = (const Rt*)z;
+    ca.m = (const Rt*)m;
+    ca.seg_begin = (const int64_t*)(w + B.seg_begin);
+    ca.seg_end = (const int64_t*)(w + B.seg_end);
+    ca.seg_slot = (const int32_t*)(w + B.seg_slot);
+    ca.n = n;
+    ca.nunits = U;
+    ca.partials = (Rt*)(w + B.L.partials);
+    ForceArgs<Rt> fa;
+    fill_force_common(fa, p);
+    fa.x = (Rt*)x;
+    fa.y = (Rt*)y;
+    fa.z = (Rt*)z;
+    fa.vx = (Rt*)vx;
+    fa.vy = (Rt*)vy;
+    fa.vz = (Rt*)vz;
+    fa.ax = (Rt*)ax;
+    fa.ay = (Rt*)ay;
+    fa.az = (Rt*)az;
+    fa.W = (const Rt*)Wb;
+    fa.n = n;
+    fa.host = hp;
+    fa.blk_cluster = (const int32_t*)(w + B.blk_cluster);
+    fa.blk_begin = (const int64_t*)(w + B.blk_begin);
+    fa.blk_end = (const int64_t*)(w + B.blk_end);
+    fa.centre_tab = (const double*)(w + B.cur);
+    fa.W_stride = W_stride;
+    // one step's kernels: coefficients of every cluster, their reduction and
+    // finalisation (which also selects this step's centre rows), then the
+    // fused field + kick (+ drift) pass
+    auto enqueue = [&](hipStream_t q, double kick, double drift, double* coef) -> scf_status {
+      {
+        Timed t(p, q, K_BATCH_COEF);
+        HIP_TRY(p->eng->launch_coef(&ca, U, v, q));
+      }
+      HIP_TRY(launch_reduce_batched(p->dtype, ca.partials, (const int32_t*)(w + B.rows), ncl,
+                                    (int)p->T, nch, (double*)(w + B.L.red1), q));
+      HIP_TRY(launch_finalize_batched(p->dtype, (const double*)(w + B.L.red1), nch, (int)p->T,
+                                      p->nmax, p->lmax, p->nmaxc, p->d_cs, p->d_fw, coef, Wb,
+                                      W_stride, (const double*)(w + B.tab), ncl,
+                                      (double*)(w + B.cur), (int*)(w + B.ctr), q));
+      ForceArgs<Rt> f2 = fa;
+      f2.kick = Rt(kick);
+      f2.drift = Rt(drift);
+      HIP_TRY(p->eng->launch_force(&f2, nblk, 1, q));
+      return SCF_OK;
+    };
+    scf_status st = upload_rows(acc_valid ? 1 : 0);
+    if (st != SCF_OK) return st;
+    int64_t chunk0 = acc_valid ? 1 : 0;
+    if (!acc_valid) {
+      // a(x0): field pass with no kick and no drift (v is rewritten unchanged)
+      st = enqueue(s, 0.0, 0.0, nsteps == 0 && coef_last ? coef_last : coef_int);
+      if (st != SCF_OK) return st;
+    }
+    if (nsteps == 0) return SCF_OK;
+    {
+      Timed t(p, s, K_KICK);
+      HIP_TRY(launch_kick_drift(p->dtype, n, x, y, z, vx, vy, vz, ax, ay, az, h, dt, s));
+    }
+    // the graph of one middle step (kick dt, drift dt), captured once per
+    // distinct argument set on the plan's capture stream
+    if (use_graph && nsteps > 1) {
+      std::vector<char> key;
+      auto add = [&](const void* q, size_t b) {
+        key.insert(key.end(), (const char*)q, (const char*)q + b);
+      };
+      add(&ca, sizeof(ca));
+      add(&fa, sizeof(fa));
+      add(&dt, sizeof(dt));
+      add(&U, sizeof(U));
+      add(&nblk, sizeof(nblk));
+      add(&nch, sizeof(nch));
+      add(&v, sizeof(v));
+      add(&coef_int, sizeof(coef_int));
+      if (!p->gexec || key != p->gkey) {
+        if (p->gexec) HIP_TRY(hipGraphExecDestroy(p->gexec));
+        if (p->graph) HIP_TRY(hipGraphDestroy(p->graph));
+        p->gexec = nullptr;
+        p->graph = nullptr;
+        p->gkey.clear();
+        if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+        scf_status cs = enqueue(p->cap_stream, dt, dt, coef_int);
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(p->cap_stream, &g);
+        if (cs != SCF_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return cs;
+        }
+        HIP_TRY(ee);
+        p->graph = g;
+        HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+        p->gkey = key;
+        p->graph_captures += 1;
+      }
+    }
+    for (int64_t k = 1; k <= nsteps; ++k) {
+      if (k - chunk0 >= kCentreRows) {
+        chunk0 = k;
+        st = upload_rows(k);
+        if (st != SCF_OK) return st;
+      }
+      const bool last = k == nsteps;
+      if (!last && use_graph) {
+        Timed t(p, s, K_BATCH_FIELD);
+        HIP_TRY(hipGraphLaunch(p->gexec, s));
+      } else {
+        st = enqueue(s, last ? h : dt, last ? 0.0 : dt, last && coef_last ? coef_last : coef_int);
+        if (st != SCF_OK) return st;
+      }
+    }
+    return SCF_OK;
+  };
+  scf_status st = p->dtype == SCF_F32 ? go(float(0)) : go(double(0));
+  HIP_TRY(hipEventRecord(p->ev_staging, s));
+  p->staging_pending = true;
+  if (st == SCF_OK) std::copy(cnew.begin(), cnew.end(), centres);
+  return st;
 }
+
+int32_t scf_plan_graph_captures(const scf_plan* p) { return p ? p->graph_captures : 0; }
 
 scf_status scf_adjoint_workspace_size(const scf_plan* p, int64_t n, int32_t nsteps, size_t* bytes) {
   (void)p; (void)n; (void)nsteps; (void)bytes;

@@ -100,5 +100,14 @@ hipError_t launch_kick_drift(int dtype, int64_t n, void* x, void* y, void* z, vo
                              void* vz, const void* ax, const void* ay, const void* az, double kick,
                              double drift, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+// batched mode (cluster-segmented) reduction and finalisation
+hipError_t launch_reduce_batched(int dtype, const void* partials, const int32_t* rows, int ncl,
+                                 int T, int nchunks, double* red1, hipStream_t s);
+hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, int T, int nmax,
+                                   int lmax, int nmaxc, const double* cs, const double* fw,
+                                   double* coef, void* W, int64_t W_stride,
+                                   const double* centre_tab, int ncl, double* cur, int* step,
+                                   hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
 
 }  // namespace scf

@@ -606,6 +606,69 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(int64_t n, R* x, R* y, 
   z[i] = fma(drift, w, z[i]);
 }
 
+// Batched reduction: cluster c owns partial rows [rows[c], rows[c+1]);
+// red1[c][chunk][t] sums its rows of one chunk (double).
+template <typename R>
+__global__ void __launch_bounds__(256) reduce_batched_kernel(const R* __restrict__ partials,
+                                                             const int32_t* __restrict__ rows,
+                                                             int T, int nchunks, double* red1) {
+  __shared__ double sh[4][64];
+  const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + ti;
+  const int c = blockIdx.z;
+  const int r0 = rows[c], r1 = rows[c + 1];
+  const int per_chunk = (r1 - r0 + nchunks - 1) / nchunks;
+  const int b0 = r0 + blockIdx.y * per_chunk;
+  int b1 = b0 + per_chunk;
+  if (b1 > r1) b1 = r1;
+  double s = 0.0;
+  if (t < T)
+    for (int b = b0 + kc; b < b1; b += 4) s += double(partials[(int64_t)b * T + t]);
+  sh[kc][ti] = s;
+  __syncthreads();
+  if (kc == 0 && t < T)
+    red1[((int64_t)c * nchunks + blockIdx.y) * T + t] =
+        ((sh[0][ti] + sh[1][ti]) + sh[2][ti]) + sh[3][ti];
+}
+
+// Batched finalisation: coef[c][t] and W[c][.] of every cluster.  Block
+// (0, 0) also copies row *step of the centre table into cur (the rows the
+// field pass of this step reads) and then advances *step.
+template <typename R>
+__global__ void __launch_bounds__(256) finalize_batched_kernel(
+    const double* __restrict__ red1, int nchunks, int T, int nmax, int lmax, int nmaxc,
+    const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W,
+    int64_t W_stride, const double* __restrict__ centre_tab, int ncl, double* cur, int* step) {
+  const int L2 = (lmax + 1) * (lmax + 1);
+  const int c = blockIdx.y;
+  if (blockIdx.x == 0 && c == 0 && step) {
+    const int k = *step;
+    for (int i = threadIdx.x; i < ncl * 9; i += blockDim.x)
+      cur[i] = centre_tab[(int64_t)k * ncl * 9 + i];
+    __syncthreads();
+    if (threadIdx.x == 0) *step = k + 1;
+  }
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (nmaxc + 1) * L2) return;
+  R* Wc = W + (int64_t)c * W_stride;
+  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
+  if (n > nmax) {
+    Wc[e] = R(0);
+    return;
+  }
+  const int t = n * L2 + lj;
+  const double* r = red1 + (int64_t)c * nchunks * T;
+  double s = 0.0;
+  for (int ch = 0; ch < nchunks; ++ch) s += r[(int64_t)ch * T + t];
+  const double cv = cs[t] * s;
+  if (coef) coef[(int64_t)c * T + t] = cv;
+  Wc[e] = R(fw[t] * cv);
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 __global__ void fill_kernel(double* p, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -661,6 +724,42 @@ hipError_t launch_kick_drift(int dtype, int64_t n, void* x, void* y, void* z, vo
     kick_drift_kernel<double><<<dim3((unsigned)grid), 256, 0, s>>>(
         n, (double*)x, (double*)y, (double*)z, (double*)vx, (double*)vy, (double*)vz,
         (const double*)ax, (const double*)ay, (const double*)az, kick, drift);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_batched(int dtype, const void* partials, const int32_t* rows, int ncl,
+                                 int T, int nchunks, double* red1, hipStream_t s) {
+  if (ncl <= 0 || T <= 0) return hipSuccess;
+  dim3 grid((T + 63) / 64, nchunks, ncl);
+  if (dtype == 0)
+    reduce_batched_kernel<float><<<grid, 256, 0, s>>>((const float*)partials, rows, T, nchunks, red1);
+  else
+    reduce_batched_kernel<double><<<grid, 256, 0, s>>>((const double*)partials, rows, T, nchunks,
+                                                       red1);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, int T, int nmax,
+                                   int lmax, int nmaxc, const double* cs, const double* fw,
+                                   double* coef, void* W, int64_t W_stride,
+                                   const double* centre_tab, int ncl, double* cur, int* step,
+                                   hipStream_t s) {
+  if (ncl <= 0) return hipSuccess;
+  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
+  dim3 grid((ne + 255) / 256, ncl);
+  if (dtype == 0)
+    finalize_batched_kernel<float><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw,
+                                                        coef, (float*)W, W_stride, centre_tab, ncl,
+                                                        cur, step);
+  else
+    finalize_batched_kernel<double><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs,
+                                                         fw, coef, (double*)W, W_stride,
+                                                         centre_tab, ncl, cur, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  set_int_kernel<<<1, 64, 0, s>>>(p, v);
   return hipGetLastError();
 }
 

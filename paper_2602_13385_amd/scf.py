@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libscf.so")
 
 F32, F64 = 0, 1
 STEP_ACC_VALID = 1
+STEP_NO_GRAPH = 2
 HOST_KINDS = {"log": 1, "hernquist": 2, "nfw": 3, "mn": 4, "plummer": 5}
 MAX_HOST_COMP = 8
 
@@ -77,6 +78,7 @@ SIGNATURES = {
     "scf_adjoint_workspace_size": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
     "scf_plan_num_variants": (C.c_int32, [_vp]),
     "scf_plan_variant": (C.c_int32, [_vp]),
+    "scf_plan_graph_captures": (C.c_int32, [_vp]),
     "scf_plan_set_variant": (C.c_int, [_vp, C.c_int32]),
     "scf_plan_describe": (C.c_char_p, [_vp]),
     "scf_autotune": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _dp]),
@@ -262,3 +264,34 @@ class Plan:
                               C.byref(h) if h is not None else None, C.cast(cen, _dp), float(dt),
                               int(nsteps), _ptr(coef_last), _ptr(ws), ws.numel(), _stream()))
         return np.array(cen[:]), acc
+
+    @property
+    def graph_captures(self):
+        return int(lib().scf_plan_graph_captures(self._h))
+
+    def step_batched(self, offsets, st, m, dt, nsteps, host=None, centres=None, acc=None,
+                     coef_last=None, graph=True):
+        """Advance nclusters clusters concatenated in st = [x, y, z, vx, vy, vz]
+        (cluster c owns [offsets[c], offsets[c+1])) in place.  centres: (nclusters, 6).
+        Returns (centres (nclusters, 6) numpy, acc)."""
+        torch = _torch()
+        self._check_arrays(*st, m)
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        ncl = len(off) - 1
+        n = int(off[-1])
+        if st[0].numel() < n:
+            raise ValueError("particle arrays shorter than offsets[-1]")
+        acc_valid = acc is not None
+        if acc is None:
+            acc = [torch.empty_like(st[0]) for _ in range(3)]
+        cen = np.zeros((ncl, 6)) if centres is None else np.array(centres, dtype=np.float64)
+        cen = np.ascontiguousarray(cen.reshape(ncl, 6))
+        h = make_host(host[0], host[1]) if host is not None else None
+        ws = self.workspace(n, nclusters=ncl, device=st[0].device)
+        flags = (STEP_ACC_VALID if acc_valid else 0) | (0 if graph else STEP_NO_GRAPH)
+        _check(lib().scf_step_batched(self._h, ncl, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      *[_ptr(t) for t in st], _ptr(m), *[_ptr(t) for t in acc],
+                                      flags, C.byref(h) if h is not None else None,
+                                      cen.ctypes.data_as(_dp), float(dt), int(nsteps),
+                                      _ptr(coef_last), _ptr(ws), ws.numel(), _stream()))
+        return cen, acc
