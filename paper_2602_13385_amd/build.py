@@ -17,8 +17,10 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libscf.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["scf_api.cpp", "scf_kernels.hip"]
-HEADERS = ["host_field.h", "scf_device.h", "scf_internal.h"]
+SOURCES = ["scf_api.cpp", "scf_small.hip", "scf_engines_f32_exact.hip",
+           "scf_engines_f32_generic.hip", "scf_engines_f64_exact.hip",
+           "scf_engines_f64_generic.hip"]
+HEADERS = ["host_field.h", "scf_device.h", "scf_dual.h", "scf_internal.h", "scf_kernels.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -43,7 +45,7 @@ def _compile(src, verbose):
     return _obj(src)
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 6) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))

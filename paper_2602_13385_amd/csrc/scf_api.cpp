@@ -177,6 +177,7 @@ struct scf_plan {
   int coef_variant = 0;
   int num_cu = 256;
   int resident[8] = {1, 1, 1, 1, 1, 1, 1, 1};  // resident wave-units per CU per variant
+  int gamma_resident = 1;                        // same for the adjoint's gamma pass
   size_t rs;  // sizeof real
   void* d_beta_rad = nullptr;
   void* d_beta_ang = nullptr;
@@ -392,14 +393,15 @@ void fill_force_common(ForceArgs<R>& fa, const scf_plan* p) {
 
 template <typename R>
 void fill_coef_common(CoefArgs<R>& ca, const scf_plan* p) {
+  using S = scalar_t<R>;
   std::memset(&ca, 0, sizeof(ca));
-  ca.beta_rad = (const R*)p->d_beta_rad;
-  ca.beta_ang = (const R*)p->d_beta_ang;
+  ca.beta_rad = (const S*)p->d_beta_rad;
+  ca.beta_ang = (const S*)p->d_beta_ang;
   ca.T = (int)p->T;
   ca.nmax = p->nmax;
-  ca.binv = R(1.0 / p->basis.b);
-  ca.alpha = R(p->basis.alpha);
-  ca.inv_alpha = R(1.0 / p->basis.alpha);
+  ca.binv = S(1.0 / p->basis.b);
+  ca.alpha = S(p->basis.alpha);
+  ca.inv_alpha = S(1.0 / p->basis.alpha);
   ca.amode = p->amode;
 }
 
@@ -481,6 +483,95 @@ scf_status run_field(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx
   fa.gcz = R(cen ? cen[5] : 0.0);
   Timed t(p, s, mode == 0 ? K_FIELD : K_STEP_FIELD);
   HIP_TRY(p->eng->launch_force(&fa, (n + 255) / 256, mode, s));
+  return SCF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+// gamma-pass launch geometry (one resident round, like the coefficient pass)
+int gamma_units(const scf_plan* p, int64_t n, int64_t* stages) {
+  if (n <= 0) {
+    *stages = 0;
+    return 0;
+  }
+  const int P = p->eng->gamma_stage_particles();
+  *stages = (n + P - 1) / P;
+  const int64_t cap = (int64_t)p->gamma_resident * p->num_cu;
+  return (int)std::min<int64_t>(*stages, std::max<int64_t>(cap, 1));
+}
+
+// Adjoint workspace: the common layout (partials sized for both passes), the
+// segment's positions X_k and force weights W_k (k = 0..nsteps), the gamma
+// weights W', velocity and acceleration scratch, the Hessian-vector kernel's
+// block sums and the per-kick host sums S_k.
+struct AdjLayout {
+  WsLayout L;
+  size_t X, Wsv, Wp, V, A, hp, S, total;
+  int64_t nblk;
+  size_t wsz;
+};
+
+AdjLayout adj_layout(const scf_plan* p, int64_t n, int nsteps) {
+  AdjLayout A;
+  int64_t st;
+  const int grows = gamma_units(p, n, &st) * p->eng->gamma_rows_per_unit();
+  A.L = ws_layout(p, n, 1, grows);
+  A.wsz = (size_t)(p->nmaxc + 1) * (p->lmax + 1) * (p->lmax + 1);
+  A.nblk = (n + 255) / 256;
+  const size_t rs = p->rs;
+  size_t off = A.L.total;
+  A.X = off;
+  off += align256((size_t)(nsteps + 1) * 3 * n * rs);
+  A.Wsv = off;
+  off += align256((size_t)(nsteps + 1) * A.wsz * rs);
+  A.Wp = off;
+  off += align256(A.wsz * rs);
+  A.V = off;
+  off += align256((size_t)3 * n * rs);
+  A.A = off;
+  off += align256((size_t)3 * n * rs);
+  A.hp = off;
+  off += align256((size_t)std::max<int64_t>(A.nblk, 1) * 32 * rs);
+  A.S = off;
+  off += align256((size_t)(nsteps + 1) * 32 * sizeof(double));
+  A.total = off;
+  return A;
+}
+
+// gamma_t = sum_i mu_i . grad b_t(x_i), mu = c (ex, ey, ez), turned into the
+// force weights W' of Eq. (total_potential) (the same scales as the forward
+// coefficients)
+template <typename R>
+scf_status run_gamma(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                     const void* ex, const void* ey, const void* ez, double c, void* Wout, char* ws,
+                     const WsLayout& L, hipStream_t s) {
+  int64_t stages;
+  const int units = gamma_units(p, n, &stages);
+  CoefArgs<Dual<R>> ca;
+  fill_coef_common(ca, p);
+  ca.x = (const R*)x;
+  ca.y = (const R*)y;
+  ca.z = (const R*)z;
+  ca.ex = (const R*)ex;
+  ca.ey = (const R*)ey;
+  ca.ez = (const R*)ez;
+  ca.escale = R(c);
+  ca.begin = 0;
+  ca.n = n;
+  ca.stages = stages;
+  ca.nunits = units;
+  ca.partials = (acc_t<Dual<R>>*)(ws + L.partials);
+  {
+    Timed t(p, s, K_ADJ);
+    HIP_TRY(p->eng->launch_gamma(&ca, units, s));
+  }
+  const int rows = units * p->eng->gamma_rows_per_unit();
+  const int nch = std::max(1, std::min(kReduceChunks, rows));
+  double* red1 = (double*)(ws + L.red1);
+  HIP_TRY(launch_reduce(p->dtype, ws + L.partials, rows, (int)p->T, nch, red1, s));
+  HIP_TRY(launch_finalize(p->dtype, red1, nch, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
+                          p->d_fw, nullptr, Wout, s));
   return SCF_OK;
 }
 
@@ -631,6 +722,7 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess && prop.multiProcessorCount > 0)
       p->num_cu = prop.multiProcessorCount;
     for (int v = 0; v < eng->coef_variants() && v < 8; ++v) p->resident[v] = eng->max_resident_units(v);
+    p->gamma_resident = eng->gamma_resident_units();
   }
   const int L1 = p->lmax + 1, NW = p->nmaxc + 1;
   std::vector<double> brad((size_t)L1 * NW, 0.0), bang((size_t)L1 * L1, 0.0);
@@ -1165,8 +1257,10 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
 int32_t scf_plan_graph_captures(const scf_plan* p) { return p ? p->graph_captures : 0; }
 
 scf_status scf_adjoint_workspace_size(const scf_plan* p, int64_t n, int32_t nsteps, size_t* bytes) {
-  (void)p; (void)n; (void)nsteps; (void)bytes;
-  return fail(SCF_ERR_UNSUPPORTED, "scf_step_adjoint: not built yet");
+  if (!p || !bytes) return fail(SCF_ERR_INVALID_ARG, "plan and bytes must be non-null");
+  if (n < 0 || nsteps < 0) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nsteps >= 0");
+  *bytes = std::max(plain_need(p, n), adj_layout(p, n, nsteps).total);
+  return SCF_OK;
 }
 
 scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* y0, const void* z0,
@@ -1174,10 +1268,178 @@ scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* 
                             const scf_host* host, const double* centre0, double dt, int32_t nsteps,
                             void* const* lam, double* lam_centre, double* grad_host, void* ws,
                             size_t ws_bytes, void* stream) {
-  (void)p; (void)n; (void)x0; (void)y0; (void)z0; (void)vx0; (void)vy0; (void)vz0; (void)m;
-  (void)host; (void)centre0; (void)dt; (void)nsteps; (void)lam; (void)lam_centre; (void)grad_host;
-  (void)ws; (void)ws_bytes; (void)stream;
-  return fail(SCF_ERR_UNSUPPORTED, "scf_step_adjoint: not built yet");
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (n < 0 || nsteps < 0) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nsteps >= 0");
+  if (!std::isfinite(dt)) return fail(SCF_ERR_INVALID_ARG, "dt is not finite");
+  if (!centre0 || !lam_centre || !lam) return fail(SCF_ERR_INVALID_ARG, "centre0, lam and lam_centre must be non-null");
+  scf_status hs = check_host(host);
+  if (hs != SCF_OK) return hs;
+  const bool with_host = host && host->ncomp > 0;
+  if (with_host && !grad_host) return fail(SCF_ERR_INVALID_ARG, "grad_host is null with a host potential");
+  if (n > 0) {
+    if (!(ptr_ok(x0) && ptr_ok(y0) && ptr_ok(z0) && ptr_ok(vx0) && ptr_ok(vy0) && ptr_ok(vz0) &&
+          ptr_ok(m)))
+      return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
+    for (int q = 0; q < 6; ++q)
+      if (!lam[q]) return fail(SCF_ERR_INVALID_ARG, "lam[%d] is null", q);
+  }
+  const AdjLayout A = adj_layout(p, n, nsteps);
+  if (!ws || ws_bytes < A.total)
+    return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", A.total, ws_bytes);
+  if (nsteps == 0) return SCF_OK;  // the identity map
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const size_t rs = p->rs;
+  HostParams<double> hd;
+  fill_host_params(hd, with_host ? host : nullptr);
+  const double h = 0.5 * dt;
+  // centre orbit (host, double): R_k at the kick times k = 0..nsteps
+  std::vector<double> Rk(3 * (size_t)(nsteps + 1));
+  {
+    double R[3] = {centre0[0], centre0[1], centre0[2]}, V[3] = {centre0[3], centre0[4], centre0[5]};
+    for (int i = 0; i < 3; ++i) Rk[i] = R[i];
+    double gc[3];
+    centre_accel(hd, R, gc);
+    for (int i = 0; i < 3; ++i) V[i] += h * gc[i];
+    for (int i = 0; i < 3; ++i) R[i] += dt * V[i];
+    for (int k = 1; k <= nsteps; ++k) {
+      for (int i = 0; i < 3; ++i) Rk[3 * k + i] = R[i];
+      if (k == nsteps) break;
+      centre_accel(hd, R, gc);
+      for (int i = 0; i < 3; ++i) V[i] += dt * gc[i];
+      for (int i = 0; i < 3; ++i) R[i] += dt * V[i];
+    }
+  }
+  auto row_of = [&](int k, double* row) {
+    double g[3] = {0, 0, 0};
+    if (with_host) host_grad<double>(hd, Rk[3 * k], Rk[3 * k + 1], Rk[3 * k + 2], g[0], g[1], g[2]);
+    for (int i = 0; i < 3; ++i) {
+      row[i] = Rk[3 * k + i];
+      row[3 + i] = g[i];
+    }
+  };
+  std::vector<double> S((size_t)(nsteps + 1) * 32, 0.0);
+  auto Xk = [&](int k, int c) -> char* { return w + A.X + ((size_t)k * 3 + c) * n * rs; };
+  auto Wk = [&](int k) -> char* { return w + A.Wsv + (size_t)k * A.wsz * rs; };
+  char* Vb[3] = {w + A.V, w + A.V + n * rs, w + A.V + 2 * n * rs};
+  char* Ab[3] = {w + A.A, w + A.A + n * rs, w + A.A + 2 * n * rs};
+
+  auto go = [&](auto tag) -> scf_status {
+    using Rt = decltype(tag);
+    HostParams<Rt> hp, none;
+    fill_host_params(hp, with_host ? host : nullptr);
+    fill_host_params(none, nullptr);
+    double row[6];
+    scf_status st;
+    if (n > 0) {
+      // ---- forward recompute of the segment, keeping X_k and W_k --------------
+      const void* src[6] = {x0, y0, z0, vx0, vy0, vz0};
+      for (int c = 0; c < 3; ++c) {
+        HIP_TRY(hipMemcpyAsync(Xk(0, c), src[c], n * rs, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(Vb[c], src[3 + c], n * rs, hipMemcpyDeviceToDevice, s));
+      }
+      row_of(0, row);
+      st = run_coeffs<Rt>(p, n, Xk(0, 0), Xk(0, 1), Xk(0, 2), m, (double*)(w + A.L.coef), Wk(0), w,
+                          A.L, s);
+      if (st != SCF_OK) return st;
+      st = run_field<Rt>(p, n, Xk(0, 0), Xk(0, 1), Xk(0, 2), Vb[0], Vb[1], Vb[2], Ab[0], Ab[1],
+                         Ab[2], nullptr, Wk(0), hp, row, 0, 0.0, 0.0, s);
+      if (st != SCF_OK) return st;
+      for (int c = 0; c < 3; ++c)
+        HIP_TRY(hipMemcpyAsync(Xk(1, c), Xk(0, c), n * rs, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(launch_kick_drift(p->dtype, n, Xk(1, 0), Xk(1, 1), Xk(1, 2), Vb[0], Vb[1], Vb[2], Ab[0],
+                                Ab[1], Ab[2], h, dt, s));
+      for (int k = 1; k <= nsteps; ++k) {
+        st = run_coeffs<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), m, (double*)(w + A.L.coef), Wk(k),
+                            w, A.L, s);
+        if (st != SCF_OK) return st;
+        if (k == nsteps) break;
+        for (int c = 0; c < 3; ++c)
+          HIP_TRY(hipMemcpyAsync(Xk(k + 1, c), Xk(k, c), n * rs, hipMemcpyDeviceToDevice, s));
+        row_of(k, row);
+        st = run_field<Rt>(p, n, Xk(k + 1, 0), Xk(k + 1, 1), Xk(k + 1, 2), Vb[0], Vb[1], Vb[2],
+                           Ab[0], Ab[1], Ab[2], nullptr, Wk(k), hp, row, 1, dt, dt, s);
+        if (st != SCF_OK) return st;
+      }
+      // ---- reverse sweep over the kicks k = nsteps..0 ---------------------------
+      for (int k = nsteps; k >= 0; --k) {
+        const double c = (k == nsteps || k == 0) ? h : dt;
+        st = run_gamma<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), lam[3], lam[4], lam[5], c,
+                           w + A.Wp, w, A.L, s);
+        if (st != SCF_OK) return st;
+        HvpArgs<Rt> ha;
+        std::memset(&ha, 0, sizeof(ha));
+        ha.x = (const Rt*)Xk(k, 0);
+        ha.y = (const Rt*)Xk(k, 1);
+        ha.z = (const Rt*)Xk(k, 2);
+        ha.lvx = (const Rt*)lam[3];
+        ha.lvy = (const Rt*)lam[4];
+        ha.lvz = (const Rt*)lam[5];
+        ha.c = Rt(c);
+        ha.lx = (Rt*)lam[0];
+        ha.ly = (Rt*)lam[1];
+        ha.lz = (Rt*)lam[2];
+        ha.W = (const Rt*)Wk(k);
+        ha.beta_rad = (const Rt*)p->d_beta_rad;
+        ha.beta_ang = (const Rt*)p->d_beta_ang;
+        ha.n = n;
+        ha.binv = Rt(1.0 / p->basis.b);
+        ha.alpha = Rt(p->basis.alpha);
+        ha.inv_alpha = Rt(1.0 / p->basis.alpha);
+        ha.amode = p->amode;
+        ha.host = hp;
+        ha.cx = Rt(Rk[3 * k]);
+        ha.cy = Rt(Rk[3 * k + 1]);
+        ha.cz = Rt(Rk[3 * k + 2]);
+        ha.partials = (Rt*)(w + A.hp);
+        {
+          Timed t(p, s, K_ADJ);
+          HIP_TRY(p->eng->launch_hvp(&ha, A.nblk, s));
+        }
+        if (with_host)
+          HIP_TRY(launch_adj_reduce(p->dtype, w + A.hp, A.nblk, (double*)(w + A.S) + 32 * k, s));
+        // coefficient part: a' = -grad sum_t W'_t b_t at X_k, then lambda_x += m a'
+        st = run_field<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), nullptr, nullptr, nullptr, Ab[0],
+                           Ab[1], Ab[2], nullptr, w + A.Wp, none, nullptr, 0, 0.0, 0.0, s);
+        if (st != SCF_OK) return st;
+        HIP_TRY(launch_adj_combine(p->dtype, n, m, Ab[0], Ab[1], Ab[2], lam[0], lam[1], lam[2],
+                                   lam[3], lam[4], lam[5], k > 0 ? dt : 0.0, s));
+      }
+      if (with_host)
+        HIP_TRY(hipMemcpyAsync(S.data(), w + A.S, S.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return SCF_OK;
+  };
+  scf_status st = p->dtype == SCF_F32 ? go(float(0)) : go(double(0));
+  if (st != SCF_OK) return st;
+  // ---- centre cotangents and host-parameter gradient (host, double) ----------
+  double* lR = lam_centre;
+  double* lV = lam_centre + 3;
+  const int nc = with_host ? host->ncomp : 0;
+  for (int k = nsteps; k >= 0; --k) {
+    const double c = (k == nsteps || k == 0) ? h : dt;
+    if (with_host) {
+      const double* Sk = S.data() + 32 * (size_t)k;
+      const double* R = &Rk[3 * k];
+      double hs[3], hn[3];
+      const double nu[3] = {c * lV[0], c * lV[1], c * lV[2]};
+      // particles: sum_i [-Hess(R + x_i) + Hess(R)] mu_i; the centre's own kick
+      host_hess_vec<double>(hd, R[0], R[1], R[2], Sk[3], Sk[4], Sk[5], hs[0], hs[1], hs[2]);
+      host_hess_vec<double>(hd, R[0], R[1], R[2], nu[0], nu[1], nu[2], hn[0], hn[1], hn[2]);
+      for (int i = 0; i < 3; ++i) lR[i] += Sk[i] + hs[i] - hn[i];
+      for (int cc = 0; cc < nc; ++cc)
+        for (int kk = 0; kk < 3; ++kk)
+          grad_host[3 * cc + kk] +=
+              Sk[6 + 3 * cc + kk] +
+              host_dgrad_dparam_dot<double>(hd, cc, kk, R[0], R[1], R[2], Sk[3], Sk[4], Sk[5]) -
+              host_dgrad_dparam_dot<double>(hd, cc, kk, R[0], R[1], R[2], nu[0], nu[1], nu[2]);
+    }
+    if (k > 0)
+      for (int i = 0; i < 3; ++i) lV[i] += dt * lR[i];
+  }
+  return SCF_OK;
 }
 
 }  // extern "C"

@@ -19,6 +19,8 @@
 #include <cmath>
 #include <type_traits>
 
+#include "scf_dual.h"
+
 namespace scf {
 
 template <typename R>
@@ -28,6 +30,31 @@ __device__ __forceinline__ R d_rcp(R v) {
 }
 template <typename R>
 __device__ __forceinline__ R d_sqrt(R v) { return std::sqrt(v); }
+template <typename R>
+__device__ __forceinline__ R d_log2(R v) { return std::log2(v); }
+template <typename R>
+__device__ __forceinline__ R d_exp2(R v) { return std::exp2(v); }
+
+// the same functions on dual numbers: value and first derivative
+template <typename T>
+__device__ __forceinline__ Dual<T> d_rcp(Dual<T> a) {
+  const T r = d_rcp(a.v);
+  return {r, -a.d * r * r};
+}
+template <typename T>
+__device__ __forceinline__ Dual<T> d_sqrt(Dual<T> a) {
+  const T s = d_sqrt(a.v);
+  return {s, s > T(0) ? a.d * T(0.5) / s : T(0)};
+}
+template <typename T>
+__device__ __forceinline__ Dual<T> d_log2(Dual<T> a) {
+  return {d_log2(a.v), a.d / (a.v * T(0.69314718055994530942))};
+}
+template <typename T>
+__device__ __forceinline__ Dual<T> d_exp2(Dual<T> a) {
+  const T e = d_exp2(a.v);
+  return {e, a.d * e * T(0.69314718055994530942)};
+}
 
 // alpha modes: 0 -> alpha = 1, 1 -> alpha = 1/2, 2 -> general 0 < alpha <= 1
 struct BasisConsts {
@@ -71,12 +98,12 @@ __device__ __forceinline__ Geom<R> make_geom(R x, R y, R z, R binv, R alpha, R i
     g.kap = s * iq * binv;
     g.dxi = R(4) * s * iq * iq * binv;
   } else {
-    R ls = s > R(0) ? std::log2(s) : R(0);
-    R t = s > R(0) ? std::exp2(ls * inv_alpha) : R(0);
-    R tos = s > R(0) ? std::exp2(ls * (inv_alpha - R(1))) : (alpha == R(1) ? R(1) : R(0));
+    R ls = s > R(0) ? d_log2(s) : R(0);
+    R t = s > R(0) ? d_exp2(ls * inv_alpha) : R(0);
+    R tos = s > R(0) ? d_exp2(ls * (inv_alpha - R(1))) : (alpha == R(1) ? R(1) : R(0));
     R q = R(1) + t;
     iq = d_rcp(q);
-    g.g0 = std::exp2(-alpha * std::log2(q));
+    g.g0 = d_exp2(-alpha * d_log2(q));
     R g02 = g.g0 * g.g0;
     g.w = s * g02;
     g.om = g02 * binv;

@@ -8,16 +8,25 @@
 #include <cstdint>
 
 #include "host_field.h"
+#include "scf_dual.h"
 
 namespace scf {
 
-// Kernel arguments of the coefficient (particle-sum) kernel.
+// Kernel arguments of the coefficient (particle-sum) kernel.  R is the
+// arithmetic type (float, double, or Dual<T> for the adjoint's gamma pass,
+// whose positions are x + eps escale (ex, ey, ez) with unit weights and whose
+// sums keep only the eps part).
 template <typename R>
 struct CoefArgs {
-  const R* x;
-  const R* y;
-  const R* z;
-  const R* m;
+  using S = scalar_t<R>;
+  const S* x;
+  const S* y;
+  const S* z;
+  const S* m;
+  const S* ex;  // dual mode: direction of the eps parts
+  const S* ey;
+  const S* ez;
+  S escale;
   const int64_t* seg_begin;  // per-block particle range [seg_begin[b], seg_end[b])
   const int64_t* seg_end;
   const int32_t* seg_slot;   // per-block output slot (partials row)
@@ -25,11 +34,11 @@ struct CoefArgs {
   int64_t stages;            // [begin, n) form `stages` stages, split evenly: unit u
                              // takes stages [u*stages/nunits, (u+1)*stages/nunits)
   int nunits;                // number of wave-units (particle ranges)
-  const R* beta_rad;         // [(lmax+1)][(NMAXC+1)]  monic Gegenbauer recurrence
-  const R* beta_ang;         // [(lmax+1)][(lmax+1)]   monic Legendre recurrence, [m][l]
-  R* partials;               // [nblocks][T]
+  const S* beta_rad;         // [(lmax+1)][(NMAXC+1)]  monic Gegenbauer recurrence
+  const S* beta_ang;         // [(lmax+1)][(lmax+1)]   monic Legendre recurrence, [m][l]
+  acc_t<R>* partials;        // [nblocks][T]
   int T, nmax;
-  R binv, alpha, inv_alpha;
+  S binv, alpha, inv_alpha;
   int amode;
 };
 
@@ -64,6 +73,30 @@ struct ForceArgs {
   int64_t W_stride;            // elements between clusters' W tables
 };
 
+// Kernel arguments of the adjoint's Hessian-vector kernel (T = float or double).
+template <typename T>
+struct HvpArgs {
+  const T* x;
+  const T* y;
+  const T* z;
+  const T* lvx;  // lambda_v: the cotangent direction is mu = c lambda_v
+  const T* lvy;
+  const T* lvz;
+  T c;
+  T* lx;  // lambda_x (accumulated)
+  T* ly;
+  T* lz;
+  const T* W;  // force weights of the coefficients at x
+  const T* beta_rad;
+  const T* beta_ang;
+  int64_t n;
+  T binv, alpha, inv_alpha;
+  int amode;
+  HostParams<T> host;
+  T cx, cy, cz;  // frame centre R
+  T* partials;   // [nblocks][32] block sums of the host terms (host present)
+};
+
 // Job descriptions handed to an engine.
 struct Engine {
   virtual ~Engine() {}
@@ -83,10 +116,21 @@ struct Engine {
   virtual hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const = 0;
   // launches the field kernel; mode 0 = forces, 1 = kick/drift step
   virtual hipError_t launch_force(const void* args, int64_t nblocks, int mode, hipStream_t s) const = 0;
+  // adjoint: the gamma pass (coefficient kernel on dual positions, one
+  // variant) and the Hessian-vector kernel
+  virtual int gamma_stage_particles() const = 0;
+  virtual int gamma_rows_per_unit() const = 0;
+  virtual int gamma_resident_units() const = 0;
+  virtual hipError_t launch_gamma(const void* args, int nunits, hipStream_t s) const = 0;
+  virtual hipError_t launch_hvp(const void* args, int64_t nblocks, hipStream_t s) const = 0;
   virtual const char* describe() const = 0;
 };
 
 Engine* find_engine(int dtype, int nmax, int lmax);
+Engine* find_engine_f32_exact(int nmax, int lmax);
+Engine* find_engine_f32_generic(int nmax, int lmax);
+Engine* find_engine_f64_exact(int nmax, int lmax);
+Engine* find_engine_f64_generic(int nmax, int lmax);
 
 // Small kernels independent of (nmax, lmax).
 hipError_t launch_reduce(int dtype, const void* partials, int nblocks, int T, int nchunks,
@@ -109,5 +153,12 @@ hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, i
                                    const double* centre_tab, int ncl, double* cur, int* step,
                                    hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
+// adjoint: lambda_x += m a', then lambda_v += drift lambda_x; and the
+// double-precision sum of the Hessian-vector kernel's 32 block sums
+hipError_t launch_adj_combine(int dtype, int64_t n, const void* m, const void* ax, const void* ay,
+                              const void* az, void* lx, void* ly, void* lz, void* lvx, void* lvy,
+                              void* lvz, double drift, hipStream_t s);
+hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, double* out,
+                             hipStream_t s);
 
 }  // namespace scf

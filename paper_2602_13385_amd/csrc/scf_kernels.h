@@ -1,4 +1,6 @@
-// HIP kernels of the SCF hot path for gfx950 (MI355X).
+// HIP kernel templates of the SCF hot path for gfx950 (MI355X), and the
+// engine that launches them for one (dtype, nmax bound, lmax).  Included by
+// the translation units that instantiate the engines.
 //
 // Coefficient pass (Sec. 2, Eq. sumanlm): a_t = -sum_k m_k psi*_t(x_k) is a
 // sum over particles of an outer product, per degree l, of the radial vector
@@ -18,6 +20,8 @@
 // are read with scalar loads, the radial sums sigma_lj = sum_n W_nlj p_n and
 // their xi-derivatives take 2 FMAs per particle-term, and the angular sums
 // follow from the same monic Legendre recurrence, its derivative and u^m.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -89,6 +93,24 @@ struct CoefShape {
   static constexpr int aoff(int l) { return AOFF + JT * (ntiles_c(l - 1, JT)); }
 };
 
+// One particle of a coefficient pass: position and weight (mass), or in the
+// gamma pass of the adjoint the dual position x + eps escale e with weight 1.
+template <typename R>
+__device__ __forceinline__ void load_particle(const CoefArgs<R>& a, int64_t i, R& x, R& y, R& z,
+                                              R& m) {
+  if constexpr (RealTraits<R>::dual) {
+    x = R(a.x[i], a.escale * a.ex[i]);
+    y = R(a.y[i], a.escale * a.ey[i]);
+    z = R(a.z[i], a.escale * a.ez[i]);
+    m = R(1);
+  } else {
+    x = a.x[i];
+    y = a.y[i];
+    z = a.z[i];
+    m = a.m[i];
+  }
+}
+
 // Wave-local ordering of LDS traffic: every wave works in its own region.
 template <int WPB>
 __device__ __forceinline__ void stage_sync() {
@@ -104,6 +126,8 @@ __device__ __forceinline__ void stage_sync() {
 template <typename R, int NMAXC, int LMAX, int LPP, int WPB>
 __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
   using S = CoefShape<R, NMAXC, LMAX, LPP>;
+  using Sc = scalar_t<R>;
+  using A = acc_t<R>;
   constexpr int P = S::P, NR = S::NR, JT = S::JT, G = S::G, KT = S::KT, KR = S::KR;
   constexpr int NT = S::NT, L1 = S::L1, PS = S::PS, DUMP = S::DUMP;
   constexpr int REG = P * PS;  // one wave's stage buffer
@@ -123,7 +147,7 @@ __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
   int grp = 0;
   int tl[KT], tj[KT], tt[KT];
   bool tv[KT];
-  R bl[KT][NR];
+  Sc bl[KT][NR];
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     int tau;
@@ -153,13 +177,13 @@ __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
     for (int n = 0; n < NR; ++n) bl[k][n] = a.beta_rad[tl[k] * NR + n];
   }
 
-  R acc[KT][NR][JT];
+  A acc[KT][NR][JT];
 #pragma unroll
   for (int k = 0; k < KT; ++k)
 #pragma unroll
     for (int i = 0; i < NR; ++i)
 #pragma unroll
-      for (int j = 0; j < JT; ++j) acc[k][i][j] = R(0);
+      for (int j = 0; j < JT; ++j) acc[k][i][j] = A(0);
 
   // particle range of this wave-unit
   const int unit = blockIdx.x * WPB + wave;
@@ -188,12 +212,7 @@ __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
   R nx = R(0), ny = R(0), nz = R(0), nm = R(0);
   {
     const int64_t gi = begin + q;
-    if (q < P && gi < end) {
-      nx = a.x[gi];
-      ny = a.y[gi];
-      nz = a.z[gi];
-      nm = a.m[gi];
-    }
+    if (q < P && gi < end) load_particle(a, gi, nx, ny, nz, nm);
   }
   for (int64_t base = begin; base < end; base += P) {
     // ---- basis phase: xi, m G_l and the angular columns ---------------------
@@ -229,13 +248,13 @@ __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
         const int mc = mv ? mm : LMAX;
         const int offc = mm > 0 ? 2 * mm - 1 : 0;
         const int offs = 2 * mm;
-        const R m2 = R(mc) * R(mc);
+        const Sc m2 = Sc(mc) * Sc(mc);
         R Q0 = R(0), Q1 = R(0);
 #pragma unroll
         for (int l = kk * LPP; l <= LMAX; ++l) {
           // gamma_lm = ((l-1)^2 - m^2) / ((2l-1)(2l-3)), used for l >= m+2
-          const R cl = l >= 2 ? R(1) / R((2 * l - 1) * (2 * l - 3)) : R(0);
-          const R gam = fma(-m2, cl, R((l - 1) * (l - 1)) * cl);
+          const Sc cl = l >= 2 ? Sc(1) / Sc((2 * l - 1) * (2 * l - 3)) : Sc(0);
+          const Sc gam = fma(-m2, cl, Sc((l - 1) * (l - 1)) * cl);
           const R qg = g.c * Q1 - gam * Q0;
           const R Q = (l == mm) ? R(1) : qg;
           Q0 = Q1;
@@ -256,10 +275,7 @@ __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
     {
       const int64_t gi = base + P + q;
       if (gi < end) {
-        nx = a.x[gi];
-        ny = a.y[gi];
-        nz = a.z[gi];
-        nm = a.m[gi];
+        load_particle(a, gi, nx, ny, nz, nm);
       } else {
         nx = ny = nz = nm = R(0);
       }
@@ -304,9 +320,11 @@ __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
 
   // ---- combine lane groups (in rounds) and write this unit's partials -------
   if constexpr (G > 1 && LDS_COMBINE) {
+    static_assert(sizeof(A) <= sizeof(R), "accumulators are combined in the stage buffer");
+    A* recA = reinterpret_cast<A*>(rec);
     for (int gg = 1; gg < G; ++gg) {
       if (grp == gg && tv[0]) {
-        R* dst = rec + tt[0] * NR * JT;
+        A* dst = recA + tt[0] * NR * JT;
 #pragma unroll
         for (int i = 0; i < NR; ++i)
 #pragma unroll
@@ -314,7 +332,7 @@ __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
       }
       stage_sync<WPB>();
       if (grp == 0 && tv[0]) {
-        const R* src = rec + tt[0] * NR * JT;
+        const A* src = recA + tt[0] * NR * JT;
 #pragma unroll
         for (int i = 0; i < NR; ++i)
 #pragma unroll
@@ -323,7 +341,7 @@ __global__ void __launch_bounds__(64 * WPB) coef_kernel(CoefArgs<R> a) {
       stage_sync<WPB>();
     }
   }
-  R* out = a.partials + ((int64_t)slot * ROWS + (LDS_COMBINE ? 0 : grp)) * a.T;
+  A* out = a.partials + ((int64_t)slot * ROWS + (LDS_COMBINE ? 0 : grp)) * a.T;
   constexpr int AL2 = L1 * L1;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
@@ -359,9 +377,139 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
   return ((int64_t)hi << 32) | (unsigned int)lo;
 }
 
+// psi_SCF and a = -grad psi_SCF at one point (zero force at the origin).
+// R is float, double or Dual<T>; the tables (W, recurrence constants) are of
+// the scalar type.  The degree loop is a real (wave-uniform) loop so that only
+// one degree's radial vector is live; the order loop is unrolled with uniform
+// exits.
+template <typename R, int NMAXC, int LMAX>
+__device__ __forceinline__ void field_eval(const R x, const R y, const R z,
+                                           const scalar_t<R>* __restrict__ W,
+                                           const scalar_t<R>* __restrict__ bR,
+                                           const scalar_t<R>* __restrict__ bA, scalar_t<R> binv,
+                                           scalar_t<R> alpha, scalar_t<R> inv_alpha, int amode,
+                                           R& psi, R& axv, R& ayv, R& azv) {
+  using Sc = scalar_t<R>;
+  constexpr int L1 = LMAX + 1, NW = NMAXC + 1;
+  Geom<R> g = make_geom<R>(x, y, z, R(binv), R(alpha), R(inv_alpha), amode);
+
+  R Er[L1], Ei[L1];
+  Er[0] = R(1);
+  Ei[0] = R(0);
+#pragma unroll
+  for (int m = 1; m <= LMAX; ++m) {
+    Er[m] = Er[m - 1] * g.ux - Ei[m - 1] * g.uy;
+    Ei[m] = Er[m - 1] * g.uy + Ei[m - 1] * g.ux;
+  }
+  R Qm1[L1], Qm2[L1], dQm1[L1], dQm2[L1];
+#pragma unroll
+  for (int m = 0; m <= LMAX; ++m) Qm1[m] = Qm2[m] = dQm1[m] = dQm2[m] = R(0);
+  psi = R(0);
+  R psir = R(0), gx = R(0), gy = R(0), gz = R(0);
+  R Gprev = R(0), Gl = g.g0;
+#pragma unroll 1
+  for (int l = 0; l <= LMAX; ++l) {
+    if (l > 0) {
+      Gprev = Gl;
+      Gl = Gl * g.w;
+    }
+    const Sc fl = Sc(l);
+    const R dGl = fl * Gprev * g.om - (Sc(2) * fl + Sc(1)) * g.kap * Gl;
+    // radial basis p_n and dp_n/dxi
+    R p[NW], dp[NW];
+    p[0] = R(1);
+    dp[0] = R(0);
+    if constexpr (NMAXC >= 1) {
+      p[1] = g.xi;
+      dp[1] = R(1);
+    }
+    const Sc* __restrict__ bRl = bR + l * NW;
+#pragma unroll
+    for (int n = 2; n <= NMAXC; ++n) {
+      const Sc b = bRl[n];
+      p[n] = g.xi * p[n - 1] - b * p[n - 2];
+      dp[n] = fma(g.xi, dp[n - 1], p[n - 1]) - b * dp[n - 2];
+    }
+    R psl = R(0), rhl = R(0), gxl = R(0), gyl = R(0), gzl = R(0);
+    const Sc* __restrict__ Wl = W + l * l * NW;
+#pragma unroll
+    for (int m = 0; m <= LMAX; ++m) {
+      if (m > l) break;
+      R Q, dQ;
+      if (l == m) {
+        Q = R(1);
+        dQ = R(0);
+      } else if (l == m + 1) {
+        Q = g.c;
+        dQ = R(1);
+      } else {
+        const Sc b = bA[m * L1 + l];
+        Q = g.c * Qm1[m] - b * Qm2[m];
+        dQ = fma(g.c, dQm1[m], Qm1[m]) - b * dQm2[m];
+      }
+      Qm2[m] = Qm1[m];
+      Qm1[m] = Q;
+      dQm2[m] = dQm1[m];
+      dQm1[m] = dQ;
+      const Sc* __restrict__ wc = Wl + (m == 0 ? 0 : 2 * m - 1) * NW;
+      R sc = R(wc[0]), dsc = R(0);
+      if constexpr (NMAXC >= 1) {
+        sc = fma(wc[1], p[1], sc);
+        dsc = R(wc[1]);
+      }
+#pragma unroll
+      for (int n = 2; n <= NMAXC; ++n) {
+        sc = fma(wc[n], p[n], sc);
+        dsc = fma(wc[n], dp[n], dsc);
+      }
+      if (m == 0) {
+        psl = fma(Q, sc, psl);
+        rhl = fma(Q, dsc, rhl);
+        gzl = fma(dQ, sc, gzl);
+      } else {
+        const Sc* __restrict__ ws = wc + NW;
+        R ss = R(ws[0]), dss = R(0);
+        if constexpr (NMAXC >= 1) {
+          ss = fma(ws[1], p[1], ss);
+          dss = R(ws[1]);
+        }
+#pragma unroll
+        for (int n = 2; n <= NMAXC; ++n) {
+          ss = fma(ws[n], p[n], ss);
+          dss = fma(ws[n], dp[n], dss);
+        }
+        const R v1 = sc * Er[m] + ss * Ei[m];
+        const R v2 = dsc * Er[m] + dss * Ei[m];
+        const R v3 = sc * Er[m - 1] + ss * Ei[m - 1];
+        const R v4 = ss * Er[m - 1] - sc * Ei[m - 1];
+        const R mQ = Sc(m) * Q;
+        psl = fma(Q, v1, psl);
+        rhl = fma(Q, v2, rhl);
+        gzl = fma(dQ, v1, gzl);
+        gxl = fma(mQ, v3, gxl);
+        gyl = fma(mQ, v4, gyl);
+      }
+    }
+    psi = fma(Gl, psl, psi);
+    psir = fma(dGl, psl, fma(Gl * g.dxi, rhl, psir));
+    gx = fma(Gl, gxl, gx);
+    gy = fma(Gl, gyl, gy);
+    gz = fma(Gl, gzl, gz);
+  }
+  // grad psi = psi_r rhat + (1/r) (Gamma - (rhat . Gamma) rhat)
+  const R rg = g.ux * gx + g.uy * gy + g.c * gz;
+  axv = R(0);
+  ayv = R(0);
+  azv = R(0);
+  if (g.r > R(0)) {
+    axv = -(psir * g.ux + g.ir * (gx - rg * g.ux));
+    ayv = -(psir * g.uy + g.ir * (gy - rg * g.uy));
+    azv = -(psir * g.c + g.ir * (gz - rg * g.c));
+  }
+}
+
 template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
 __global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
-  constexpr int L1 = LMAX + 1, NW = NMAXC + 1;
   int64_t i;
   const R* __restrict__ W = a.W;
   R cx = a.cx, cy = a.cy, cz = a.cz, gcx = a.gcx, gcy = a.gcy, gcz = a.gcz;
@@ -384,123 +532,10 @@ __global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
     i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
   }
-  const R* __restrict__ bR = a.beta_rad;
-  const R* __restrict__ bA = a.beta_ang;
   const R x = a.x[i], y = a.y[i], z = a.z[i];
-  Geom<R> g = make_geom<R>(x, y, z, a.binv, a.alpha, a.inv_alpha, a.amode);
-
-  R Er[L1], Ei[L1];
-  Er[0] = R(1);
-  Ei[0] = R(0);
-#pragma unroll
-  for (int m = 1; m <= LMAX; ++m) {
-    Er[m] = Er[m - 1] * g.ux - Ei[m - 1] * g.uy;
-    Ei[m] = Er[m - 1] * g.uy + Ei[m - 1] * g.ux;
-  }
-  R Qm1[L1], Qm2[L1], dQm1[L1], dQm2[L1];
-#pragma unroll
-  for (int m = 0; m <= LMAX; ++m) Qm1[m] = Qm2[m] = dQm1[m] = dQm2[m] = R(0);
-  R psi = R(0), psir = R(0), gx = R(0), gy = R(0), gz = R(0);
-  R Gprev = R(0), Gl = g.g0;
-  // The degree loop is a real (wave-uniform) loop so that only one degree's
-  // radial vector is live; the order loop is unrolled with uniform exits.
-#pragma unroll 1
-  for (int l = 0; l <= LMAX; ++l) {
-    if (l > 0) {
-      Gprev = Gl;
-      Gl = Gl * g.w;
-    }
-    const R fl = R(l);
-    const R dGl = fl * Gprev * g.om - (R(2) * fl + R(1)) * g.kap * Gl;
-    // radial basis p_n and dp_n/dxi
-    R p[NW], dp[NW];
-    p[0] = R(1);
-    dp[0] = R(0);
-    if constexpr (NMAXC >= 1) {
-      p[1] = g.xi;
-      dp[1] = R(1);
-    }
-    const R* __restrict__ bRl = bR + l * NW;
-#pragma unroll
-    for (int n = 2; n <= NMAXC; ++n) {
-      const R b = bRl[n];
-      p[n] = g.xi * p[n - 1] - b * p[n - 2];
-      dp[n] = fma(g.xi, dp[n - 1], p[n - 1]) - b * dp[n - 2];
-    }
-    R psl = R(0), rhl = R(0), gxl = R(0), gyl = R(0), gzl = R(0);
-    const R* __restrict__ Wl = W + l * l * NW;
-#pragma unroll
-    for (int m = 0; m <= LMAX; ++m) {
-      if (m > l) break;
-      R Q, dQ;
-      if (l == m) {
-        Q = R(1);
-        dQ = R(0);
-      } else if (l == m + 1) {
-        Q = g.c;
-        dQ = R(1);
-      } else {
-        const R b = bA[m * L1 + l];
-        Q = g.c * Qm1[m] - b * Qm2[m];
-        dQ = fma(g.c, dQm1[m], Qm1[m]) - b * dQm2[m];
-      }
-      Qm2[m] = Qm1[m];
-      Qm1[m] = Q;
-      dQm2[m] = dQm1[m];
-      dQm1[m] = dQ;
-      const R* __restrict__ wc = Wl + (m == 0 ? 0 : 2 * m - 1) * NW;
-      R sc = wc[0], dsc = R(0);
-      if constexpr (NMAXC >= 1) {
-        sc = fma(wc[1], p[1], sc);
-        dsc = wc[1];
-      }
-#pragma unroll
-      for (int n = 2; n <= NMAXC; ++n) {
-        sc = fma(wc[n], p[n], sc);
-        dsc = fma(wc[n], dp[n], dsc);
-      }
-      if (m == 0) {
-        psl = fma(Q, sc, psl);
-        rhl = fma(Q, dsc, rhl);
-        gzl = fma(dQ, sc, gzl);
-      } else {
-        const R* __restrict__ ws = wc + NW;
-        R ss = ws[0], dss = R(0);
-        if constexpr (NMAXC >= 1) {
-          ss = fma(ws[1], p[1], ss);
-          dss = ws[1];
-        }
-#pragma unroll
-        for (int n = 2; n <= NMAXC; ++n) {
-          ss = fma(ws[n], p[n], ss);
-          dss = fma(ws[n], dp[n], dss);
-        }
-        const R v1 = sc * Er[m] + ss * Ei[m];
-        const R v2 = dsc * Er[m] + dss * Ei[m];
-        const R v3 = sc * Er[m - 1] + ss * Ei[m - 1];
-        const R v4 = ss * Er[m - 1] - sc * Ei[m - 1];
-        const R mQ = R(m) * Q;
-        psl = fma(Q, v1, psl);
-        rhl = fma(Q, v2, rhl);
-        gzl = fma(dQ, v1, gzl);
-        gxl = fma(mQ, v3, gxl);
-        gyl = fma(mQ, v4, gyl);
-      }
-    }
-    psi = fma(Gl, psl, psi);
-    psir = fma(dGl, psl, fma(Gl * g.dxi, rhl, psir));
-    gx = fma(Gl, gxl, gx);
-    gy = fma(Gl, gyl, gy);
-    gz = fma(Gl, gzl, gz);
-  }
-  // grad psi = psi_r rhat + (1/r) (Gamma - (rhat . Gamma) rhat)
-  const R rg = g.ux * gx + g.uy * gy + g.c * gz;
-  R axv = R(0), ayv = R(0), azv = R(0);
-  if (g.r > R(0)) {
-    axv = -(psir * g.ux + g.ir * (gx - rg * g.ux));
-    ayv = -(psir * g.uy + g.ir * (gy - rg * g.uy));
-    azv = -(psir * g.c + g.ir * (gz - rg * g.c));
-  }
+  R psi, axv, ayv, azv;
+  field_eval<R, NMAXC, LMAX>(x, y, z, W, a.beta_rad, a.beta_ang, a.binv, a.alpha, a.inv_alpha,
+                             a.amode, psi, axv, ayv, azv);
   if (a.host.ncomp > 0) {
     R hx, hy, hz;
     host_grad<R>(a.host, cx + x, cy + y, cz + z, hx, hy, hz);
@@ -531,242 +566,79 @@ __global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// small kernels
-// ---------------------------------------------------------------------------
-// partial sums over blocks: red1[chunk][t] = sum_{b in chunk} partials[b][t] (double)
-template <typename R>
-__global__ void __launch_bounds__(256) reduce_kernel(const R* __restrict__ partials, int nblocks,
-                                                     int T, int per_chunk, double* red1) {
-  __shared__ double sh[4][64];
-  const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
-  const int t = blockIdx.x * 64 + ti;
-  const int b0 = blockIdx.y * per_chunk;
-  int b1 = b0 + per_chunk;
-  if (b1 > nblocks) b1 = nblocks;
-  double s = 0.0;
-  if (t < T)
-    for (int b = b0 + kc; b < b1; b += 4) s += double(partials[(int64_t)b * T + t]);
-  sh[kc][ti] = s;
-  __syncthreads();
-  if (kc == 0 && t < T)
-    red1[(int64_t)blockIdx.y * T + t] = ((sh[0][ti] + sh[1][ti]) + sh[2][ti]) + sh[3][ti];
+// sum over the 64 lanes of a wave (every lane receives the total)
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ red1, int nchunks,
-                                                       int T, int nmax, int lmax, int nmaxc,
-                                                       const double* __restrict__ cs,
-                                                       const double* __restrict__ fw, double* coef,
-                                                       R* W) {
-  const int L2 = (lmax + 1) * (lmax + 1);
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // over (NMAXC+1) * L2 W entries
-  if (e >= (nmaxc + 1) * L2) return;
-  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
-  if (n > nmax) {
-    W[e] = R(0);
-    return;
-  }
-  const int t = n * L2 + lj;
-  double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += red1[(int64_t)c * T + t];
-  const double cv = cs[t] * s;
-  if (coef) coef[t] = cv;
-  W[e] = R(fw[t] * cv);
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) make_w_kernel(const double* __restrict__ coef, int T, int nmax,
-                                                     int lmax, int nmaxc,
-                                                     const double* __restrict__ fw, R* W) {
-  const int L2 = (lmax + 1) * (lmax + 1);
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (nmaxc + 1) * L2) return;
-  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
-  if (n > nmax) {
-    W[e] = R(0);
-    return;
-  }
-  const int t = n * L2 + lj;
-  W[e] = R(fw[t] * coef[t]);
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) kick_drift_kernel(int64_t n, R* x, R* y, R* z, R* vx, R* vy,
-                                                         R* vz, const R* ax, const R* ay,
-                                                         const R* az, R kick, R drift) {
+// Adjoint kernel of one kick at positions x_k with cotangent direction
+// mu_i = c lambda_v,i (the Hessian-vector part of the vector-Jacobian product
+// of the acceleration):
+//   lambda_x,i += d/deps a(x_i + eps mu_i)
+//              = -Hess psi_SCF(x_i) mu_i - Hess psi_host(R + x_i) mu_i,
+// the SCF part by evaluating the field on dual numbers.  With a host, each
+// block also writes the sums over its particles of -Hess psi_host(R + x_i) mu_i
+// (3), mu_i (3) and -mu_i . d grad psi_host(R + x_i) / d p_ck (3 per
+// component) to partials[block][0..31], in the order listed.
+template <typename T, int NMAXC, int LMAX>
+__global__ void __launch_bounds__(256) hvp_kernel(HvpArgs<T> a) {
+  using D = Dual<T>;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  R u = fma(kick, ax[i], vx[i]), v = fma(kick, ay[i], vy[i]), w = fma(kick, az[i], vz[i]);
-  vx[i] = u;
-  vy[i] = v;
-  vz[i] = w;
-  x[i] = fma(drift, u, x[i]);
-  y[i] = fma(drift, v, y[i]);
-  z[i] = fma(drift, w, z[i]);
-}
-
-// Batched reduction: cluster c owns partial rows [rows[c], rows[c+1]);
-// red1[c][chunk][t] sums its rows of one chunk (double).
-template <typename R>
-__global__ void __launch_bounds__(256) reduce_batched_kernel(const R* __restrict__ partials,
-                                                             const int32_t* __restrict__ rows,
-                                                             int T, int nchunks, double* red1) {
-  __shared__ double sh[4][64];
-  const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
-  const int t = blockIdx.x * 64 + ti;
-  const int c = blockIdx.z;
-  const int r0 = rows[c], r1 = rows[c + 1];
-  const int per_chunk = (r1 - r0 + nchunks - 1) / nchunks;
-  const int b0 = r0 + blockIdx.y * per_chunk;
-  int b1 = b0 + per_chunk;
-  if (b1 > r1) b1 = r1;
-  double s = 0.0;
-  if (t < T)
-    for (int b = b0 + kc; b < b1; b += 4) s += double(partials[(int64_t)b * T + t]);
-  sh[kc][ti] = s;
-  __syncthreads();
-  if (kc == 0 && t < T)
-    red1[((int64_t)c * nchunks + blockIdx.y) * T + t] =
-        ((sh[0][ti] + sh[1][ti]) + sh[2][ti]) + sh[3][ti];
-}
-
-// Batched finalisation: coef[c][t] and W[c][.] of every cluster.  Block
-// (0, 0) also copies row *step of the centre table into cur (the rows the
-// field pass of this step reads) and then advances *step.
-template <typename R>
-__global__ void __launch_bounds__(256) finalize_batched_kernel(
-    const double* __restrict__ red1, int nchunks, int T, int nmax, int lmax, int nmaxc,
-    const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W,
-    int64_t W_stride, const double* __restrict__ centre_tab, int ncl, double* cur, int* step) {
-  const int L2 = (lmax + 1) * (lmax + 1);
-  const int c = blockIdx.y;
-  if (blockIdx.x == 0 && c == 0 && step) {
-    const int k = *step;
-    for (int i = threadIdx.x; i < ncl * 9; i += blockDim.x)
-      cur[i] = centre_tab[(int64_t)k * ncl * 9 + i];
+  const bool valid = i < a.n;
+  const int64_t ii = valid ? i : 0;
+  const T x = a.x[ii], y = a.y[ii], z = a.z[ii];
+  T mx = valid ? a.c * a.lvx[ii] : T(0);
+  T my = valid ? a.c * a.lvy[ii] : T(0);
+  T mz = valid ? a.c * a.lvz[ii] : T(0);
+  D psi, ax, ay, az;
+  field_eval<D, NMAXC, LMAX>(D(x, mx), D(y, my), D(z, mz), a.W, a.beta_rad, a.beta_ang, a.binv,
+                             a.alpha, a.inv_alpha, a.amode, psi, ax, ay, az);
+  T ox = ax.d, oy = ay.d, oz = az.d;
+  if (a.host.ncomp > 0) {
+    __shared__ T red[4][32];
+    T v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) v[q] = T(0);
+    const T px = a.cx + x, py = a.cy + y, pz = a.cz + z;
+    T hx, hy, hz;
+    host_hess_vec<T>(a.host, px, py, pz, mx, my, mz, hx, hy, hz);
+    ox -= hx;
+    oy -= hy;
+    oz -= hz;
+    if (valid) {
+      v[0] = -hx;
+      v[1] = -hy;
+      v[2] = -hz;
+      v[3] = mx;
+      v[4] = my;
+      v[5] = mz;
+#pragma unroll
+      for (int c = 0; c < kMaxHostComp; ++c)
+        if (c < a.host.ncomp)
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            v[6 + 3 * c + k] = -host_dgrad_dparam_dot<T>(a.host, c, k, px, py, pz, mx, my, mz);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const T t = wave_sum(v[q]);
+      if (lane == q) red[wave][q] = t;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) *step = k + 1;
+    if (threadIdx.x < 32) {
+      const int q = threadIdx.x;
+      a.partials[(int64_t)blockIdx.x * 32 + q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    }
   }
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (nmaxc + 1) * L2) return;
-  R* Wc = W + (int64_t)c * W_stride;
-  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
-  if (n > nmax) {
-    Wc[e] = R(0);
-    return;
+  if (valid) {
+    a.lx[i] += ox;
+    a.ly[i] += oy;
+    a.lz[i] += oz;
   }
-  const int t = n * L2 + lj;
-  const double* r = red1 + (int64_t)c * nchunks * T;
-  double s = 0.0;
-  for (int ch = 0; ch < nchunks; ++ch) s += r[(int64_t)ch * T + t];
-  const double cv = cs[t] * s;
-  if (coef) coef[(int64_t)c * T + t] = cv;
-  Wc[e] = R(fw[t] * cv);
-}
-
-__global__ void set_int_kernel(int* p, int v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
-}
-
-__global__ void fill_kernel(double* p, int64_t n, double v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-hipError_t launch_reduce(int dtype, const void* partials, int nblocks, int T, int nchunks,
-                         double* red1, hipStream_t s) {
-  if (nblocks <= 0 || T <= 0) return hipSuccess;
-  const int per_chunk = (nblocks + nchunks - 1) / nchunks;
-  dim3 grid((T + 63) / 64, nchunks);
-  if (dtype == 0)
-    reduce_kernel<float><<<grid, 256, 0, s>>>((const float*)partials, nblocks, T, per_chunk, red1);
-  else
-    reduce_kernel<double><<<grid, 256, 0, s>>>((const double*)partials, nblocks, T, per_chunk, red1);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize(int dtype, const double* red1, int nchunks, int T, int nmax, int lmax,
-                           int nmaxc, const double* cs, const double* fw, double* coef, void* W,
-                           hipStream_t s) {
-  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
-  const int grid = (ne + 255) / 256;
-  if (dtype == 0)
-    finalize_kernel<float><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw, coef,
-                                                (float*)W);
-  else
-    finalize_kernel<double><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw, coef,
-                                                 (double*)W);
-  return hipGetLastError();
-}
-
-hipError_t launch_make_w(int dtype, const double* coef, int T, int nmax, int lmax, int nmaxc,
-                         const double* fw, void* W, hipStream_t s) {
-  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
-  const int grid = (ne + 255) / 256;
-  if (dtype == 0)
-    make_w_kernel<float><<<grid, 256, 0, s>>>(coef, T, nmax, lmax, nmaxc, fw, (float*)W);
-  else
-    make_w_kernel<double><<<grid, 256, 0, s>>>(coef, T, nmax, lmax, nmaxc, fw, (double*)W);
-  return hipGetLastError();
-}
-
-hipError_t launch_kick_drift(int dtype, int64_t n, void* x, void* y, void* z, void* vx, void* vy,
-                             void* vz, const void* ax, const void* ay, const void* az, double kick,
-                             double drift, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const int64_t grid = (n + 255) / 256;
-  if (dtype == 0)
-    kick_drift_kernel<float><<<dim3((unsigned)grid), 256, 0, s>>>(
-        n, (float*)x, (float*)y, (float*)z, (float*)vx, (float*)vy, (float*)vz, (const float*)ax,
-        (const float*)ay, (const float*)az, (float)kick, (float)drift);
-  else
-    kick_drift_kernel<double><<<dim3((unsigned)grid), 256, 0, s>>>(
-        n, (double*)x, (double*)y, (double*)z, (double*)vx, (double*)vy, (double*)vz,
-        (const double*)ax, (const double*)ay, (const double*)az, kick, drift);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_batched(int dtype, const void* partials, const int32_t* rows, int ncl,
-                                 int T, int nchunks, double* red1, hipStream_t s) {
-  if (ncl <= 0 || T <= 0) return hipSuccess;
-  dim3 grid((T + 63) / 64, nchunks, ncl);
-  if (dtype == 0)
-    reduce_batched_kernel<float><<<grid, 256, 0, s>>>((const float*)partials, rows, T, nchunks, red1);
-  else
-    reduce_batched_kernel<double><<<grid, 256, 0, s>>>((const double*)partials, rows, T, nchunks,
-                                                       red1);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, int T, int nmax,
-                                   int lmax, int nmaxc, const double* cs, const double* fw,
-                                   double* coef, void* W, int64_t W_stride,
-                                   const double* centre_tab, int ncl, double* cur, int* step,
-                                   hipStream_t s) {
-  if (ncl <= 0) return hipSuccess;
-  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
-  dim3 grid((ne + 255) / 256, ncl);
-  if (dtype == 0)
-    finalize_batched_kernel<float><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw,
-                                                        coef, (float*)W, W_stride, centre_tab, ncl,
-                                                        cur, step);
-  else
-    finalize_batched_kernel<double><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs,
-                                                         fw, coef, (double*)W, W_stride,
-                                                         centre_tab, ncl, cur, step);
-  return hipGetLastError();
-}
-
-hipError_t launch_set_int(int* p, int v, hipStream_t s) {
-  set_int_kernel<<<1, 64, 0, s>>>(p, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  fill_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(p, n, v);
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -845,6 +717,31 @@ struct EngineImpl final : Engine {
       field_kernel<R, NMAXC, LMAX, 1, false><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
     return hipGetLastError();
   }
+  // adjoint gamma pass: variant 0's lane split on dual numbers
+  using GS = CoefShape<Dual<R>, NMAXC, LMAX, V::LPP[0]>;
+  int gamma_stage_particles() const override { return GS::P; }
+  int gamma_rows_per_unit() const override {
+    return (GS::G == 1 || GS::NT * GS::NR * GS::JT <= GS::P * GS::PS) ? 1 : GS::G;
+  }
+  int gamma_resident_units() const override {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, coef_kernel<Dual<R>, NMAXC, LMAX, V::LPP[0], 1>, 64, 0);
+    if (e != hipSuccess || per_cu <= 0) per_cu = 1;
+    return per_cu;
+  }
+  hipError_t launch_gamma(const void* args, int nunits, hipStream_t s) const override {
+    if (nunits <= 0) return hipSuccess;
+    const CoefArgs<Dual<R>>& ca = *(const CoefArgs<Dual<R>>*)args;
+    coef_kernel<Dual<R>, NMAXC, LMAX, V::LPP[0], 1><<<nunits, 64, 0, s>>>(ca);
+    return hipGetLastError();
+  }
+  hipError_t launch_hvp(const void* args, int64_t nblocks, hipStream_t s) const override {
+    if (nblocks <= 0) return hipSuccess;
+    const HvpArgs<R>& ha = *(const HvpArgs<R>*)args;
+    hvp_kernel<R, NMAXC, LMAX><<<dim3((unsigned)nblocks), 256, 0, s>>>(ha);
+    return hipGetLastError();
+  }
   const char* describe() const override {
     static char buf[200];
     using S0 = CoefShape<R, NMAXC, LMAX, V::LPP[0]>;
@@ -856,39 +753,5 @@ struct EngineImpl final : Engine {
     return buf;
   }
 };
-
-#define SCF_ENGINE(R, N, L)                      \
-  if (nmax <= N && lmax == L && exact == (N == nmax)) { \
-    static EngineImpl<R, N, L> e;                \
-    return &e;                                   \
-  }
-
-template <typename R>
-static Engine* find_engine_t(int nmax, int lmax, bool exact) {
-  // exact-size instances for the shipped workloads
-  SCF_ENGINE(R, 6, 4)
-  SCF_ENGINE(R, 10, 5)
-  SCF_ENGINE(R, 10, 6)
-  SCF_ENGINE(R, 16, 10)
-  // generic instances: any nmax <= 20 for these degrees
-  SCF_ENGINE(R, 20, 0)
-  SCF_ENGINE(R, 20, 1)
-  SCF_ENGINE(R, 20, 2)
-  SCF_ENGINE(R, 20, 3)
-  SCF_ENGINE(R, 20, 4)
-  SCF_ENGINE(R, 20, 5)
-  SCF_ENGINE(R, 20, 6)
-  SCF_ENGINE(R, 20, 8)
-  SCF_ENGINE(R, 20, 10)
-  return nullptr;
-}
-#undef SCF_ENGINE
-
-Engine* find_engine(int dtype, int nmax, int lmax) {
-  if (nmax < 0 || lmax < 0) return nullptr;
-  Engine* e = dtype == 0 ? find_engine_t<float>(nmax, lmax, true) : find_engine_t<double>(nmax, lmax, true);
-  if (e) return e;
-  return dtype == 0 ? find_engine_t<float>(nmax, lmax, false) : find_engine_t<double>(nmax, lmax, false);
-}
 
 }  // namespace scf

@@ -1,0 +1,325 @@
+// Small kernels of the SCF hot path that do not depend on (nmax, lmax): the
+// double-precision cross-block reductions of the coefficient sums, the force
+// weights, the standalone kick-drift, fills, the batched-mode reductions and
+// the adjoint's combination and reduction kernels; and the engine lookup.
+#include <hip/hip_runtime.h>
+
+#include "scf_internal.h"
+
+namespace scf {
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+// partial sums over blocks: red1[chunk][t] = sum_{b in chunk} partials[b][t] (double)
+template <typename R>
+__global__ void __launch_bounds__(256) reduce_kernel(const R* __restrict__ partials, int nblocks,
+                                                     int T, int per_chunk, double* red1) {
+  __shared__ double sh[4][64];
+  const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + ti;
+  const int b0 = blockIdx.y * per_chunk;
+  int b1 = b0 + per_chunk;
+  if (b1 > nblocks) b1 = nblocks;
+  double s = 0.0;
+  if (t < T)
+    for (int b = b0 + kc; b < b1; b += 4) s += double(partials[(int64_t)b * T + t]);
+  sh[kc][ti] = s;
+  __syncthreads();
+  if (kc == 0 && t < T)
+    red1[(int64_t)blockIdx.y * T + t] = ((sh[0][ti] + sh[1][ti]) + sh[2][ti]) + sh[3][ti];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ red1, int nchunks,
+                                                       int T, int nmax, int lmax, int nmaxc,
+                                                       const double* __restrict__ cs,
+                                                       const double* __restrict__ fw, double* coef,
+                                                       R* W) {
+  const int L2 = (lmax + 1) * (lmax + 1);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // over (NMAXC+1) * L2 W entries
+  if (e >= (nmaxc + 1) * L2) return;
+  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
+  if (n > nmax) {
+    W[e] = R(0);
+    return;
+  }
+  const int t = n * L2 + lj;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += red1[(int64_t)c * T + t];
+  const double cv = cs[t] * s;
+  if (coef) coef[t] = cv;
+  W[e] = R(fw[t] * cv);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) make_w_kernel(const double* __restrict__ coef, int T, int nmax,
+                                                     int lmax, int nmaxc,
+                                                     const double* __restrict__ fw, R* W) {
+  const int L2 = (lmax + 1) * (lmax + 1);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (nmaxc + 1) * L2) return;
+  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
+  if (n > nmax) {
+    W[e] = R(0);
+    return;
+  }
+  const int t = n * L2 + lj;
+  W[e] = R(fw[t] * coef[t]);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) kick_drift_kernel(int64_t n, R* x, R* y, R* z, R* vx, R* vy,
+                                                         R* vz, const R* ax, const R* ay,
+                                                         const R* az, R kick, R drift) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  R u = fma(kick, ax[i], vx[i]), v = fma(kick, ay[i], vy[i]), w = fma(kick, az[i], vz[i]);
+  vx[i] = u;
+  vy[i] = v;
+  vz[i] = w;
+  x[i] = fma(drift, u, x[i]);
+  y[i] = fma(drift, v, y[i]);
+  z[i] = fma(drift, w, z[i]);
+}
+
+// Batched reduction: cluster c owns partial rows [rows[c], rows[c+1]);
+// red1[c][chunk][t] sums its rows of one chunk (double).
+template <typename R>
+__global__ void __launch_bounds__(256) reduce_batched_kernel(const R* __restrict__ partials,
+                                                             const int32_t* __restrict__ rows,
+                                                             int T, int nchunks, double* red1) {
+  __shared__ double sh[4][64];
+  const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + ti;
+  const int c = blockIdx.z;
+  const int r0 = rows[c], r1 = rows[c + 1];
+  const int per_chunk = (r1 - r0 + nchunks - 1) / nchunks;
+  const int b0 = r0 + blockIdx.y * per_chunk;
+  int b1 = b0 + per_chunk;
+  if (b1 > r1) b1 = r1;
+  double s = 0.0;
+  if (t < T)
+    for (int b = b0 + kc; b < b1; b += 4) s += double(partials[(int64_t)b * T + t]);
+  sh[kc][ti] = s;
+  __syncthreads();
+  if (kc == 0 && t < T)
+    red1[((int64_t)c * nchunks + blockIdx.y) * T + t] =
+        ((sh[0][ti] + sh[1][ti]) + sh[2][ti]) + sh[3][ti];
+}
+
+// Batched finalisation: coef[c][t] and W[c][.] of every cluster.  Block
+// (0, 0) also copies row *step of the centre table into cur (the rows the
+// field pass of this step reads) and then advances *step.
+template <typename R>
+__global__ void __launch_bounds__(256) finalize_batched_kernel(
+    const double* __restrict__ red1, int nchunks, int T, int nmax, int lmax, int nmaxc,
+    const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W,
+    int64_t W_stride, const double* __restrict__ centre_tab, int ncl, double* cur, int* step) {
+  const int L2 = (lmax + 1) * (lmax + 1);
+  const int c = blockIdx.y;
+  if (blockIdx.x == 0 && c == 0 && step) {
+    const int k = *step;
+    for (int i = threadIdx.x; i < ncl * 9; i += blockDim.x)
+      cur[i] = centre_tab[(int64_t)k * ncl * 9 + i];
+    __syncthreads();
+    if (threadIdx.x == 0) *step = k + 1;
+  }
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (nmaxc + 1) * L2) return;
+  R* Wc = W + (int64_t)c * W_stride;
+  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
+  if (n > nmax) {
+    Wc[e] = R(0);
+    return;
+  }
+  const int t = n * L2 + lj;
+  const double* r = red1 + (int64_t)c * nchunks * T;
+  double s = 0.0;
+  for (int ch = 0; ch < nchunks; ++ch) s += r[(int64_t)ch * T + t];
+  const double cv = cs[t] * s;
+  if (coef) coef[(int64_t)c * T + t] = cv;
+  Wc[e] = R(fw[t] * cv);
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_reduce(int dtype, const void* partials, int nblocks, int T, int nchunks,
+                         double* red1, hipStream_t s) {
+  if (nblocks <= 0 || T <= 0) return hipSuccess;
+  const int per_chunk = (nblocks + nchunks - 1) / nchunks;
+  dim3 grid((T + 63) / 64, nchunks);
+  if (dtype == 0)
+    reduce_kernel<float><<<grid, 256, 0, s>>>((const float*)partials, nblocks, T, per_chunk, red1);
+  else
+    reduce_kernel<double><<<grid, 256, 0, s>>>((const double*)partials, nblocks, T, per_chunk, red1);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(int dtype, const double* red1, int nchunks, int T, int nmax, int lmax,
+                           int nmaxc, const double* cs, const double* fw, double* coef, void* W,
+                           hipStream_t s) {
+  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
+  const int grid = (ne + 255) / 256;
+  if (dtype == 0)
+    finalize_kernel<float><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw, coef,
+                                                (float*)W);
+  else
+    finalize_kernel<double><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw, coef,
+                                                 (double*)W);
+  return hipGetLastError();
+}
+
+hipError_t launch_make_w(int dtype, const double* coef, int T, int nmax, int lmax, int nmaxc,
+                         const double* fw, void* W, hipStream_t s) {
+  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
+  const int grid = (ne + 255) / 256;
+  if (dtype == 0)
+    make_w_kernel<float><<<grid, 256, 0, s>>>(coef, T, nmax, lmax, nmaxc, fw, (float*)W);
+  else
+    make_w_kernel<double><<<grid, 256, 0, s>>>(coef, T, nmax, lmax, nmaxc, fw, (double*)W);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(int dtype, int64_t n, void* x, void* y, void* z, void* vx, void* vy,
+                             void* vz, const void* ax, const void* ay, const void* az, double kick,
+                             double drift, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t grid = (n + 255) / 256;
+  if (dtype == 0)
+    kick_drift_kernel<float><<<dim3((unsigned)grid), 256, 0, s>>>(
+        n, (float*)x, (float*)y, (float*)z, (float*)vx, (float*)vy, (float*)vz, (const float*)ax,
+        (const float*)ay, (const float*)az, (float)kick, (float)drift);
+  else
+    kick_drift_kernel<double><<<dim3((unsigned)grid), 256, 0, s>>>(
+        n, (double*)x, (double*)y, (double*)z, (double*)vx, (double*)vy, (double*)vz,
+        (const double*)ax, (const double*)ay, (const double*)az, kick, drift);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_batched(int dtype, const void* partials, const int32_t* rows, int ncl,
+                                 int T, int nchunks, double* red1, hipStream_t s) {
+  if (ncl <= 0 || T <= 0) return hipSuccess;
+  dim3 grid((T + 63) / 64, nchunks, ncl);
+  if (dtype == 0)
+    reduce_batched_kernel<float><<<grid, 256, 0, s>>>((const float*)partials, rows, T, nchunks, red1);
+  else
+    reduce_batched_kernel<double><<<grid, 256, 0, s>>>((const double*)partials, rows, T, nchunks,
+                                                       red1);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, int T, int nmax,
+                                   int lmax, int nmaxc, const double* cs, const double* fw,
+                                   double* coef, void* W, int64_t W_stride,
+                                   const double* centre_tab, int ncl, double* cur, int* step,
+                                   hipStream_t s) {
+  if (ncl <= 0) return hipSuccess;
+  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
+  dim3 grid((ne + 255) / 256, ncl);
+  if (dtype == 0)
+    finalize_batched_kernel<float><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw,
+                                                        coef, (float*)W, W_stride, centre_tab, ncl,
+                                                        cur, step);
+  else
+    finalize_batched_kernel<double><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs,
+                                                         fw, coef, (double*)W, W_stride,
+                                                         centre_tab, ncl, cur, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  set_int_kernel<<<1, 64, 0, s>>>(p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// adjoint helpers
+// ---------------------------------------------------------------------------
+// lambda_x += m a' (the coefficient part of the vector-Jacobian product, with
+// a' the field of the gamma-weighted coefficients), then, when drift != 0,
+// lambda_v += drift lambda_x (the reverse of the drift that precedes the kick)
+template <typename R>
+__global__ void __launch_bounds__(256) adj_combine_kernel(int64_t n, const R* __restrict__ m,
+                                                          const R* __restrict__ ax,
+                                                          const R* __restrict__ ay,
+                                                          const R* __restrict__ az, R* lx, R* ly,
+                                                          R* lz, R* lvx, R* lvy, R* lvz, R drift) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const R mi = m[i];
+  const R x = fma(mi, ax[i], lx[i]), y = fma(mi, ay[i], ly[i]), z = fma(mi, az[i], lz[i]);
+  lx[i] = x;
+  ly[i] = y;
+  lz[i] = z;
+  if (drift != R(0)) {
+    lvx[i] = fma(drift, x, lvx[i]);
+    lvy[i] = fma(drift, y, lvy[i]);
+    lvz[i] = fma(drift, z, lvz[i]);
+  }
+}
+
+// out[q] = sum over blocks of partials[b][q], q < 32, in double and in a fixed
+// order (8 strided block subsets, then their sum)
+template <typename R>
+__global__ void __launch_bounds__(256) adj_reduce_kernel(const R* __restrict__ partials,
+                                                         int64_t nblocks, double* out) {
+  __shared__ double sh[8][32];
+  const int q = threadIdx.x & 31, part = threadIdx.x >> 5;
+  double s = 0.0;
+  for (int64_t b = part; b < nblocks; b += 8) s += double(partials[b * 32 + q]);
+  sh[part][q] = s;
+  __syncthreads();
+  if (part == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 8; ++k) t += sh[k][q];
+    out[q] = t;
+  }
+}
+
+hipError_t launch_adj_combine(int dtype, int64_t n, const void* m, const void* ax, const void* ay,
+                              const void* az, void* lx, void* ly, void* lz, void* lvx, void* lvy,
+                              void* lvz, double drift, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (dtype == 0)
+    adj_combine_kernel<float><<<grid, 256, 0, s>>>(
+        n, (const float*)m, (const float*)ax, (const float*)ay, (const float*)az, (float*)lx,
+        (float*)ly, (float*)lz, (float*)lvx, (float*)lvy, (float*)lvz, (float)drift);
+  else
+    adj_combine_kernel<double><<<grid, 256, 0, s>>>(
+        n, (const double*)m, (const double*)ax, (const double*)ay, (const double*)az, (double*)lx,
+        (double*)ly, (double*)lz, (double*)lvx, (double*)lvy, (double*)lvz, drift);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, double* out,
+                             hipStream_t s) {
+  if (dtype == 0)
+    adj_reduce_kernel<float><<<1, 256, 0, s>>>((const float*)partials, nblocks, out);
+  else
+    adj_reduce_kernel<double><<<1, 256, 0, s>>>((const double*)partials, nblocks, out);
+  return hipGetLastError();
+}
+
+Engine* find_engine(int dtype, int nmax, int lmax) {
+  if (nmax < 0 || lmax < 0) return nullptr;
+  Engine* e = dtype == 0 ? find_engine_f32_exact(nmax, lmax) : find_engine_f64_exact(nmax, lmax);
+  if (e) return e;
+  return dtype == 0 ? find_engine_f32_generic(nmax, lmax) : find_engine_f64_generic(nmax, lmax);
+}
+
+}  // namespace scf

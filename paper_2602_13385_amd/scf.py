@@ -265,6 +265,37 @@ class Plan:
                               int(nsteps), _ptr(coef_last), _ptr(ws), ws.numel(), _stream()))
         return np.array(cen[:]), acc
 
+    def adjoint_workspace(self, n, nsteps, device=None):
+        torch = _torch()
+        need = C.c_size_t()
+        _check(lib().scf_adjoint_workspace_size(self._h, int(n), int(nsteps), C.byref(need)))
+        if self._ws is None or self._ws.numel() < need.value:
+            self._ws = torch.empty(max(need.value, 256), dtype=torch.uint8,
+                                   device=device or torch.device("cuda"))
+        return self._ws
+
+    def step_adjoint(self, st0, m, dt, nsteps, lam, lam_centre, host=None, centre0=None):
+        """Reverse mode of step() over nsteps steps starting from the synchronised
+        state st0 = [x, y, z, vx, vy, vz] (not modified).  lam: 6 device tensors
+        holding dL/d(final state), overwritten with dL/d(initial state).
+        lam_centre: (6,) dL/d(final R, V).  Returns (dL/d(initial R, V) (6,),
+        dL/d(host parameters) (ncomp, 3))."""
+        self._check_arrays(*st0, m, *lam)
+        n = st0[0].numel()
+        h = make_host(host[0], host[1]) if host is not None else None
+        ncomp = h.ncomp if h is not None else 0
+        cen = (C.c_double * 6)(*[float(v) for v in (centre0 if centre0 is not None else np.zeros(6))])
+        lc = (C.c_double * 6)(*[float(v) for v in lam_centre])
+        gh = (C.c_double * max(3 * ncomp, 1))()
+        lp = (C.c_void_p * 6)(*[t.data_ptr() for t in lam])
+        ws = self.adjoint_workspace(n, nsteps, device=st0[0].device)
+        _check(lib().scf_step_adjoint(self._h, n, *[_ptr(t) for t in st0], _ptr(m),
+                                      C.byref(h) if h is not None else None, C.cast(cen, _dp),
+                                      float(dt), int(nsteps), C.cast(lp, C.POINTER(C.c_void_p)),
+                                      C.cast(lc, _dp), C.cast(gh, _dp), _ptr(ws), ws.numel(),
+                                      _stream()))
+        return np.array(lc[:]), np.array(gh[:3 * ncomp]).reshape(ncomp, 3)
+
     @property
     def graph_captures(self):
         return int(lib().scf_plan_graph_captures(self._h))

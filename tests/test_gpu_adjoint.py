@@ -1,0 +1,165 @@
+"""GPU checks of scf_step_adjoint and the checkpointed autograd wrapper.
+
+  * against the FP64 oracle's exact discrete adjoint of the same leapfrog map
+    (same FP32-representable inputs): FP64 to 1e-9, FP32 to the gradient bar
+    1e-3 (componentwise for the host-parameter and centre gradients);
+  * against central finite differences of the GPU's own FP64 forward map,
+    through the torch.autograd.Function with recomputation from checkpoints;
+  * checkpointed and single-segment backward passes agree.
+"""
+import numpy as np
+import pytest
+
+from paper_2602_13385_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+NFW = [("nfw", (232.98, 20.0))]
+CEN = np.array([20.0, 0.0, 0.0, 0.1, 1.4, 0.3])
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2602_13385_amd import scf
+    scf.lib()
+    return scf
+
+
+def _rounded(arr, dtype):
+    a = np.asarray(arr, dtype=np.float64)
+    return a.astype(np.float32).astype(np.float64) if dtype == "f32" else a
+
+
+def _dev(torch, arr, dtype):
+    td = torch.float32 if dtype == "f32" else torch.float64
+    return torch.as_tensor(np.ascontiguousarray(arr), dtype=td, device="cuda")
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("dtype,host", [("f64", True), ("f32", True), ("f64", False),
+                                        ("f32", False)])
+def test_adjoint_matches_oracle(torch, S, O, dtype, host):
+    n, nmax, lmax, dt, nsteps = 3000, 10, 6, 0.005, 4
+    print(f"[adjoint parity] {dtype} host={host}", flush=True)
+    p = I.plummer(n, 5501)
+    st0 = _rounded(p.state(), dtype)
+    m = _rounded(p.mass, dtype)
+    rng = np.random.default_rng(5502)
+    lam = _rounded(rng.normal(size=(6, n)), dtype)
+    lamc = rng.normal(size=6)
+    B = O.basis(nmax, lmax)
+    Ho = O.host([(O.HOST_NFW, NFW[0][1])]) if host else None
+    cen = CEN if host else np.zeros(6)
+    lam_ref, lc_ref, gh_ref = O.step_adjoint(B, Ho, st0, m, cen, dt, nsteps, lam, lamc)
+    plan = S.Plan(nmax, lmax, dtype=dtype)
+    st = [_dev(torch, st0[i], dtype) for i in range(6)]
+    lt = [_dev(torch, lam[i], dtype) for i in range(6)]
+    lc, gh = plan.step_adjoint(st, _dev(torch, m, dtype), dt, nsteps, lt, lamc,
+                               host=(NFW, 1.0) if host else None, centre0=cen)
+    torch.cuda.synchronize()
+    lg = np.stack([t.cpu().numpy() for t in lt]).astype(np.float64)
+    # the state is not modified
+    assert np.array_equal(np.stack([t.cpu().numpy() for t in st]).astype(np.float64), st0)
+    tol = 1e-9 if dtype == "f64" else 1e-3
+    assert _rel(lg[:3], lam_ref[:3]) <= tol, _rel(lg[:3], lam_ref[:3])
+    assert _rel(lg[3:], lam_ref[3:]) <= tol, _rel(lg[3:], lam_ref[3:])
+    for q in range(6):
+        assert abs(lc[q] - lc_ref[q]) <= tol * max(abs(lc_ref[q]), 1e-6 * np.abs(lc_ref).max()), q
+    if host:
+        assert gh.shape == (1, 3)
+        for k in range(2):
+            assert abs(gh[0, k] - gh_ref[0, k]) <= tol * abs(gh_ref[0, k]), (k, gh, gh_ref)
+
+
+def test_adjoint_zero_steps_is_identity(torch, S):
+    p = I.plummer(500, 5503)
+    plan = S.Plan(6, 4, dtype="f64")
+    st = [_dev(torch, p.state()[i], "f64") for i in range(6)]
+    lam = [torch.randn(500, dtype=torch.float64, device="cuda") for _ in range(6)]
+    ref = [t.clone() for t in lam]
+    lc, gh = plan.step_adjoint(st, _dev(torch, p.mass, "f64"), 0.01, 0, lam, np.arange(6.0),
+                               host=(NFW, 1.0), centre0=CEN)
+    assert np.array_equal(lc, np.arange(6.0))
+    assert np.all(gh == 0.0)
+    for a, b in zip(lam, ref):
+        assert torch.equal(a, b)
+
+
+def _functional(torch, n, seed):
+    rng = np.random.default_rng(seed)
+    w = torch.as_tensor(rng.normal(size=(6, n)), dtype=torch.float64, device="cuda")
+    c = torch.as_tensor(rng.normal(size=6), dtype=torch.float64)
+    return w, c
+
+
+def test_autograd_checkpoints_match_finite_differences(torch, S):
+    from paper_2602_13385_amd import adjoint as A
+    n, dt, nsteps = 2000, 0.005, 5
+    p = I.plummer(n, 5504)
+    plan = S.Plan(10, 6, dtype="f64")
+    m = _dev(torch, p.mass, "f64")
+    st0 = _dev(torch, p.state(), "f64")
+    w, c = _functional(torch, n, 5505)
+
+    def loss(theta, cen0, checkpoint=2, grad=False):
+        s0 = st0.clone().requires_grad_(grad)
+        sT, cT = A.trajectory(plan, s0, m, theta, cen0, ["nfw"], dt, nsteps, checkpoint)
+        return (w * sT).sum() + (c * cT).sum(), s0
+
+    theta = torch.tensor([[232.98, 20.0, 0.0]], dtype=torch.float64, requires_grad=True)
+    cen0 = torch.tensor(CEN, dtype=torch.float64, requires_grad=True)
+    L, s0 = loss(theta, cen0, grad=True)
+    L.backward()
+    g_theta = theta.grad.numpy().copy()
+    g_cen = cen0.grad.numpy().copy()
+    g_s0 = s0.grad.detach().cpu().numpy()
+    # single segment gives the same gradient
+    theta2 = theta.detach().clone().requires_grad_(True)
+    cen2 = cen0.detach().clone().requires_grad_(True)
+    L2, _ = loss(theta2, cen2, checkpoint=nsteps)
+    L2.backward()
+    assert np.abs(theta2.grad.numpy() - g_theta).max() <= 1e-10 * np.abs(g_theta).max()
+    assert np.abs(cen2.grad.numpy() - g_cen).max() <= 1e-10 * np.abs(g_cen).max()
+    # central differences of the FP64 forward map
+    with torch.no_grad():
+        def Lnum(th, ce):
+            return float(loss(th, ce)[0])
+        for k, hrel in ((0, 1e-6), (1, 1e-6)):
+            h = hrel * abs(float(theta[0, k]))
+            tp, tm = theta.detach().clone(), theta.detach().clone()
+            tp[0, k] += h
+            tm[0, k] -= h
+            fd = (Lnum(tp, cen0.detach()) - Lnum(tm, cen0.detach())) / (2 * h)
+            assert abs(fd - g_theta[0, k]) <= 1e-5 * abs(g_theta[0, k]) + 1e-9, (k, fd, g_theta)
+        for q in range(6):
+            h = 1e-5
+            cp, cm = cen0.detach().clone(), cen0.detach().clone()
+            cp[q] += h
+            cm[q] -= h
+            fd = (Lnum(theta.detach(), cp) - Lnum(theta.detach(), cm)) / (2 * h)
+            assert abs(fd - g_cen[q]) <= 1e-5 * np.abs(g_cen).max(), (q, fd, g_cen)
+        # one particle coordinate
+        for (row, i) in ((0, 17), (4, 1234)):
+            h = 1e-6
+            base = st0.clone()
+            sp, sm = base.clone(), base.clone()
+            sp[row, i] += h
+            sm[row, i] -= h
+
+            def Ls(s):
+                sT, cT = A.trajectory(plan, s, m, theta.detach(), cen0.detach(), ["nfw"], dt,
+                                      nsteps, 2)
+                return float((w * sT).sum() + (c * cT).sum())
+            fd = (Ls(sp) - Ls(sm)) / (2 * h)
+            assert abs(fd - g_s0[row, i]) <= 1e-5 * max(abs(g_s0[row, i]), 1e-3), (row, i, fd)
