@@ -4,10 +4,17 @@
 A step is one pass of the whole hot path over the workload: coefficient
 accumulation (Eq. sumanlm) with its FP64 cross-block reduction, the field
 evaluation (Eq. total_potential and its gradient, plus the host tidal field
-when there is a host) and the fused leapfrog kick-drift.  The workload is the
-Hernquist sphere N = 1e6 with nmax = 16, lmax = 10 (T = 2057 real
-coefficients), inputs resident in HBM.  The metric is particle x basis-term
-evaluations per second, N * T * steps / time.
+when there is a host) and the fused leapfrog kick-drift.  The headline
+workload is the Hernquist sphere N = 1e6 with nmax = 16, lmax = 10 (T = 2057
+real coefficients), inputs resident in HBM.  The metric is particle x
+basis-term evaluations per second, N * T * steps / time, in FP32.
+
+Also reported on the same JSON line: the FP64 path on the same workload, the
+batched path (10 Plummer progenitors in a composite host, one graph launch per
+step, against the summed plain per-cluster steps), the adjoint/forward time
+ratio of the checkpointed reverse pass (Plummer N = 1e5 in an NFW host, 2000
+steps, checkpoints every 100), the FP32 path's relative errors, and the FP64
+CPU oracle timed on a bounded sample.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -22,9 +29,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak (counts packed FP32)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
 METRIC = "particle×basis-term evals/s per step (FP32 vs FP64); adjoint/forward time ratio"
+KERNEL_FILES = ("scf_kernels.h", "scf_device.h", "scf_dual.h", "host_field.h")
 
 
 def algorithmic_flops(nmax, lmax, host_flops=0):
@@ -37,15 +46,15 @@ def algorithmic_flops(nmax, lmax, host_flops=0):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("scf_kernels.hip", "scf_device.h", "host_field.h"):
+    for f in KERNEL_FILES:
         with open(os.path.join(ROOT, "paper_2602_13385_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, n_launch):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source; else None."""
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -57,7 +66,20 @@ def measured_traffic(kernel, n_launch):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def run_gpu(dtype, steps, warmup, torch, scf, I, profile):
+def _timed(torch, fn):
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    out = fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return out, e0.elapsed_time(e1)
+
+
+def run_main(dtype, steps, warmup, torch, scf, I, profile):
+    """Hernquist N = 1e6, nmax 16, lmax 10: `steps` timed steps."""
     w = I.config3()
     p = w.clusters[0]
     td = torch.float32 if dtype == "f32" else torch.float64
@@ -65,6 +87,7 @@ def run_gpu(dtype, steps, warmup, torch, scf, I, profile):
     st = [dev(p.state()[i]) for i in range(6)]
     m = dev(p.mass)
     plan = scf.Plan(w.nmax, w.lmax, alpha=w.alpha, b=w.b, G=w.G, dtype=dtype)
+    variant, _ = plan.autotune(st[0], st[1], st[2], m)
     n = p.n
     cen, acc = plan.step(st, m, w.dt, 1)  # start-up evaluation of a(x0)
     if warmup:
@@ -73,23 +96,140 @@ def run_gpu(dtype, steps, warmup, torch, scf, I, profile):
     if profile:
         plan.profile(True)
         plan.kernel_times()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    (cen, acc), ms = _timed(torch, lambda: plan.step(st, m, w.dt, steps, centre=cen, acc=acc))
+    wall = time.perf_counter() - t0
+    kt = plan.kernel_times() if profile else {}
+    if profile:
+        plan.profile(False)
+    return {"n": n, "T": plan.T, "nmax": w.nmax, "lmax": w.lmax, "ms": ms, "wall_s": wall,
+            "kernels": kt, "dt": w.dt, "name": w.name, "variant": variant, "plan": plan,
+            "describe": plan.describe()}
+
+
+def accuracy_main(torch, scf, I):
+    """FP32 vs FP64 coefficients and forces on the headline workload, and the
+    FP64 potential against the closed-form Hernquist potential -1/(1+r)."""
+    import numpy as np
+    w = I.config3()
+    p = w.clusters[0]
+    out = {}
+    res = {}
+    for dtype, td in (("f32", torch.float32), ("f64", torch.float64)):
+        pos = np.asarray(p.pos, dtype=np.float32).astype(np.float64)
+        mass = np.asarray(p.mass, dtype=np.float32).astype(np.float64)
+        x, y, z = (torch.as_tensor(pos[i], dtype=td, device="cuda") for i in range(3))
+        m = torch.as_tensor(mass, dtype=td, device="cuda")
+        plan = scf.Plan(w.nmax, w.lmax, dtype=dtype)
+        c = plan.coeffs(x, y, z, m)
+        ax, ay, az, pot = plan.forces(x, y, z, c, pot=True)
+        torch.cuda.synchronize()
+        res[dtype] = (c.cpu().numpy(), np.stack([t.double().cpu().numpy() for t in (ax, ay, az)]),
+                      pot.double().cpu().numpy())
+    c32, g32, _ = res["f32"]
+    c64, g64, p64 = res["f64"]
+    out["coef_relerr_f32_vs_f64"] = float(np.abs(c32 - c64).max() / np.abs(c64).max())
+    mag = np.sqrt((g64 ** 2).sum(0))
+    d = np.sqrt(((g32 - g64) ** 2).sum(0))
+    out["force_relerr_f32_vs_f64"] = float((d / (mag + np.median(mag))).max())
+    r = np.sqrt((np.asarray(p.pos) ** 2).sum(0))
+    ref = -1.0 / (1.0 + r)
+    out["pot_relerr_f64_vs_closed_form_median"] = float(np.median(np.abs(p64 - ref) / np.abs(ref)))
+    out["note"] = ("f32 vs f64: same FP32-representable inputs; closed form: N = 1e6 Monte-Carlo "
+                   "sample, so the difference is sampling noise of the truncated expansion")
+    return out
+
+
+def run_batched(torch, scf, I, steps):
+    """10 Plummer progenitors (N log-uniform in [2e4, 5e5]) on eccentric orbits
+    in the composite host: batched graph launches vs the summed plain steps."""
+    import numpy as np
+    w = I.config4()
+    sizes = [c.n for c in w.clusters]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    state = np.concatenate([c.state() for c in w.clusters], axis=1)
+    mass = np.concatenate([c.mass for c in w.clusters])
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    st = [dev(state[i]) for i in range(6)]
+    m = dev(mass)
+    cens = np.array(w.centres)
+    plan = scf.Plan(w.nmax, w.lmax, dtype="f32")
+    plan.autotune(st[0], st[1], st[2], m)
+    host = (w.host, w.G)
+    cen, acc = plan.step_batched(off, st, m, w.dt, 3, host=host, centres=cens)
+    (cen, acc), ms = _timed(torch, lambda: plan.step_batched(off, st, m, w.dt, steps, host=host,
+                                                             centres=cen, acc=acc))
+    # plain per-cluster steps on the same GPU, same particles
+    parts = []
+    for c in range(len(sizes)):
+        sl = slice(off[c], off[c + 1])
+        parts.append(([dev(state[i, sl]) for i in range(6)], dev(mass[sl]), cens[c]))
+    accs = []
+    cs = []
+    for stc, mc, cc in parts:
+        c1, a1 = plan.step(stc, mc, w.dt, 3, host=host, centre=cc)
+        accs.append(a1)
+        cs.append(c1)
+
+    def plain():
+        for k, (stc, mc, _) in enumerate(parts):
+            cs[k], accs[k] = plan.step(stc, mc, w.dt, steps, host=host, centre=cs[k], acc=accs[k])
+    _, ms_plain = _timed(torch, plain)
+    N = int(off[-1])
+    T = plan.T
+    return {"workload": w.name, "N_total": N, "clusters": len(sizes), "steps": steps,
+            "value": N * T * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+            "plain_per_cluster_value": N * T * steps / (ms_plain * 1e-3),
+            "plain_per_cluster_ms_per_step": ms_plain / steps,
+            "speedup_vs_plain": ms_plain / ms, "graph_captures": plan.graph_captures}
+
+
+def run_adjoint(torch, scf, I, nsteps=None):
+    """Plummer N = 1e5 in an NFW host, 2000 steps with checkpoints every 100:
+    forward and backward times of the checkpointed autograd trajectory."""
+    import numpy as np
+    from paper_2602_13385_amd import adjoint as A
+    w = I.config5()
+    p = w.clusters[0]
+    nsteps = nsteps or w.nsteps
+    ck = w.extra["checkpoint"]
+    track = w.extra["track"]
+    plan = scf.Plan(w.nmax, w.lmax, dtype="f32")
+    m = torch.as_tensor(p.mass, dtype=torch.float32, device="cuda")
+    s0 = torch.as_tensor(p.state(), dtype=torch.float32, device="cuda").contiguous()
+    theta = torch.tensor([list(w.host[0][1])], dtype=torch.float64, requires_grad=True)
+    cen0 = torch.tensor(w.centres[0], dtype=torch.float64, requires_grad=True)
+    plan.autotune(s0[0].contiguous(), s0[1].contiguous(), s0[2].contiguous(), m)
+    kinds = [w.host[0][0]]
+    # base trajectory: frozen escaper set and nearest track points
+    with torch.no_grad():
+        sT, cT = A.trajectory(plan, s0, m, theta.detach(), cen0.detach(), kinds, w.dt, nsteps, ck)
+        mask = A.escaped_mask(plan, sT, m)
+        idx = A.nearest_track_points(sT, cT.numpy(), track, mask)
+    s0g = s0.clone().requires_grad_(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    cen, acc = plan.step(st, m, w.dt, steps, centre=cen, acc=acc)
-    e1.record(stream)
+    sT, cT = A.trajectory(plan, s0g, m, theta, cen0, kinds, w.dt, nsteps, ck)
+    L = A.track_loss(sT, cT, track, mask, idx)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    kt = plan.kernel_times() if profile else {}
-    return {"n": n, "T": plan.T, "nmax": w.nmax, "lmax": w.lmax, "ms": ms, "wall_s": wall,
-            "kernels": kt, "dt": w.dt, "name": w.name}
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    g = theta.grad.numpy()[0]
+    return {"workload": w.name, "N": p.n, "steps": nsteps, "checkpoint": ck,
+            "forward_s": t_fwd, "backward_s": t_bwd, "adjoint_forward_ratio": t_bwd / t_fwd,
+            "escapers": int(mask.sum().item()), "loss": float(L.item()),
+            "dL_dM_s": float(g[0]), "dL_dr_s": float(g[1]),
+            "dL_dcentre0": [float(v) for v in cen0.grad.numpy()],
+            "timing": "wall clock around the autograd forward (checkpointed scf_step segments + "
+                      "loss) and backward (scf_step_adjoint per segment, recompute included)"}
 
 
-def cpu_baseline(nsample=200_000):
+def cpu_baseline(nsample=1_000_000, reps=2):
+    """The FP64 oracle (OpenMP over the host's cores) on `reps` coefficient +
+    field passes over the headline workload's particles."""
     from oracle import pyoracle as O
     from paper_2602_13385_amd import inputs as I
     w = I.config3()
@@ -98,13 +238,14 @@ def cpu_baseline(nsample=200_000):
     pos = p.pos[:, :nsample].copy()
     mass = p.mass[:nsample].copy()
     t0 = time.perf_counter()
-    c = O.coeffs(B, *pos, mass)
-    O.field(B, c, *pos, pot=False)
+    for _ in range(reps):
+        c = O.coeffs(B, *pos, mass)
+        O.field(B, c, *pos, pot=False)
     t = time.perf_counter() - t0
     T = O.ncoef(w.nmax, w.lmax)
-    return {"value": nsample * T / t, "unit": "particle-terms/s", "cores": O.num_threads(),
+    return {"value": reps * nsample * T / t, "unit": "particle-terms/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"one coefficient + field pass of the FP64 oracle over the first {nsample} "
+            "sample": f"{reps} coefficient + field passes of the FP64 oracle over the {nsample} "
                       f"particles of the Hernquist N=1e6 nmax=16 lmax=10 workload ({t:.1f} s)"}
 
 
@@ -115,12 +256,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline FP32 workload only (no FP64, batched, adjoint, accuracy)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs the hot path on one GPU only; --gpus {args.gpus} is not "
-              f"supported (see the sharding notes in DESIGN.md)", file=sys.stderr)
+              f"supported (the multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -140,19 +283,25 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
         return
     scf.lib()
-    r = run_gpu("f32", args.steps, args.warmup, torch, scf, I, profile=True)
+    print("[bench] headline FP32", file=sys.stderr, flush=True)
+    r = run_main("f32", args.steps, args.warmup, torch, scf, I, profile=True)
     n, T = r["n"], r["T"]
     ms_per_step = r["ms"] / args.steps
     value = n * T * args.steps / (r["ms"] * 1e-3)
     fl = algorithmic_flops(r["nmax"], r["lmax"])
-    # dominant kernel: the larger of the coefficient and field passes
     kt = r["kernels"]
-    cands = {k: v for k, v in kt.items() if k in ("coef", "field_step")}
-    dom = max(cands, key=lambda k: cands[k][1])
-    cnt, tot = cands[dom]
-    avg_s = tot / cnt * 1e-3
-    achieved = fl[dom] * n / avg_s / 1e12
-    traffic = measured_traffic(dom, n)
+    per_kernel = {}
+    for k in ("coef", "field_step"):
+        if k in kt:
+            cnt, tot = kt[k]
+            avg_s = tot / cnt * 1e-3
+            tf = fl[k] * n / avg_s / 1e12
+            per_kernel[k] = {"avg_launch_ms": tot / cnt, "tflops": tf,
+                             "frac": tf / PEAK_FP32_TFLOPS,
+                             "frac_nonpacked": tf / PEAK_FP32_NONPACKED_TFLOPS}
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_launch_ms"])
+    achieved = per_kernel[dom]["tflops"]
+    step_tf = (fl["coef"] + fl["field_step"]) * n / (ms_per_step * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": value,
@@ -167,20 +316,38 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": r["name"], "N": n, "nmax": r["nmax"], "lmax": r["lmax"], "T": T,
-                   "alpha": 1.0, "dt": r["dt"], "host": None},
+                   "alpha": 1.0, "dt": r["dt"], "host": None, "coef_variant": r["variant"]},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": traffic, "flops_per_launch": fl[dom] * n,
-                     "avg_launch_ms": tot / cnt},
+                     "traffic": measured_traffic(dom), "flops_per_launch": fl[dom] * n,
+                     "avg_launch_ms": per_kernel[dom]["avg_launch_ms"],
+                     "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                     "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS},
+        "kernels": per_kernel,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
-        "step_tflops": (fl["coef"] + fl["field_step"]) * n / (ms_per_step * 1e-3) / 1e12,
+        "step_tflops": step_tf,
+        "step_frac": step_tf / PEAK_FP32_TFLOPS,
     }
-    if not args.no_f64:
-        steps64 = max(1, args.steps // 4)
-        r64 = run_gpu("f64", steps64, max(1, args.warmup // 4), torch, scf, I, profile=False)
-        out["f64"] = {"value": n * T * steps64 / (r64["ms"] * 1e-3), "ms_per_step": r64["ms"] / steps64,
-                      "steps": steps64}
+    del r["plan"]
+    if not args.no_extras:
+        if not args.no_f64:
+            print("[bench] FP64", file=sys.stderr, flush=True)
+            steps64 = max(1, args.steps // 4)
+            r64 = run_main("f64", steps64, max(1, args.warmup // 4), torch, scf, I, profile=False)
+            tf64 = (fl["coef"] + fl["field_step"]) * n / (r64["ms"] / steps64 * 1e-3) / 1e12
+            out["f64"] = {"value": n * T * steps64 / (r64["ms"] * 1e-3),
+                          "ms_per_step": r64["ms"] / steps64, "steps": steps64,
+                          "step_tflops": tf64, "frac_fp64_peak": tf64 / PEAK_FP64_TFLOPS,
+                          "f32_over_f64_speed": (r64["ms"] / steps64) / ms_per_step}
+            del r64["plan"]
+        print("[bench] accuracy", file=sys.stderr, flush=True)
+        out["accuracy"] = accuracy_main(torch, scf, I)
+        print("[bench] batched", file=sys.stderr, flush=True)
+        out["batched"] = run_batched(torch, scf, I, steps=50)
+        print("[bench] adjoint", file=sys.stderr, flush=True)
+        out["adjoint"] = run_adjoint(torch, scf, I)
     if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
     else:
         out["cpu_baseline"] = None

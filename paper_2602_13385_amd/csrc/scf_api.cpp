@@ -223,7 +223,8 @@ struct Timed {
   int kind;
   hipEvent_t b = nullptr;
   Timed(scf_plan* p_, hipStream_t s_, int k) : p(p_), s(s_), kind(k) {
-    if (p && p->prof && p->ev_next + 2 <= p->ev_pool.size() && s != p->cap_stream) {
+    if (p && p->prof && p->ev_next + 2 <= p->ev_pool.size() &&
+        !(p->cap_stream && s == p->cap_stream)) {
       hipEvent_t a = p->ev_pool[p->ev_next++];
       b = p->ev_pool[p->ev_next++];
       (void)hipEventRecord(a, s);
