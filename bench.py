@@ -206,6 +206,12 @@ def run_adjoint(torch, scf, I, nsteps=None):
         sT, cT = A.trajectory(plan, s0, m, theta.detach(), cen0.detach(), kinds, w.dt, nsteps, ck)
         mask = A.escaped_mask(plan, sT, m)
         idx = A.nearest_track_points(sT, cT.numpy(), track, mask)
+    # warm-up: one untimed forward and backward of the same trajectory
+    # (workspace, checkpoint buffers and kernel loading)
+    th_w = theta.detach().clone().requires_grad_(True)
+    sw, cw = A.trajectory(plan, s0.clone().requires_grad_(True), m, th_w, cen0.detach(), kinds,
+                          w.dt, nsteps, ck)
+    A.track_loss(sw, cw, track, mask, idx).backward()
     s0g = s0.clone().requires_grad_(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

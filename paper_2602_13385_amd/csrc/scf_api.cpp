@@ -269,7 +269,7 @@ int coef_blocks_max(const scf_plan* p, int64_t n) {
   return nb;
 }
 
-constexpr int kReduceChunks = 16;
+constexpr int kReduceChunks = 64;
 
 struct WsLayout {
   size_t partials, red1, coef, W, total;
@@ -453,17 +453,25 @@ scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
   return SCF_OK;
 }
 
+// Field pass over n particles.  mode 0: a (and psi) into ax, ay, az (pot);
+// mode 1: kick by `kick`, drift by `drift` with the drifted positions written
+// to xo (default: in place); mode 2: adjoint accumulation (see field_kernel).
 template <typename R>
 scf_status run_field(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx, void* vy,
                      void* vz, void* ax, void* ay, void* az, void* pot, const void* W,
                      const HostParams<R>& hp, const double* cen, int mode, double kick,
-                     double drift, hipStream_t s) {
+                     double drift, hipStream_t s, void* xo = nullptr, void* yo = nullptr,
+                     void* zo = nullptr, const void* mass = nullptr) {
   if (n == 0) return SCF_OK;
   ForceArgs<R> fa;
   fill_force_common(fa, p);
   fa.x = (R*)x;
   fa.y = (R*)y;
   fa.z = (R*)z;
+  fa.xo = (R*)(xo ? xo : x);
+  fa.yo = (R*)(yo ? yo : y);
+  fa.zo = (R*)(zo ? zo : z);
+  fa.mass = (const R*)mass;
   fa.vx = (R*)vx;
   fa.vy = (R*)vy;
   fa.vz = (R*)vz;
@@ -482,7 +490,7 @@ scf_status run_field(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx
   fa.gcx = R(cen ? cen[3] : 0.0);
   fa.gcy = R(cen ? cen[4] : 0.0);
   fa.gcz = R(cen ? cen[5] : 0.0);
-  Timed t(p, s, mode == 0 ? K_FIELD : K_STEP_FIELD);
+  Timed t(p, s, mode == 0 ? K_FIELD : (mode == 1 ? K_STEP_FIELD : K_ADJ));
   HIP_TRY(p->eng->launch_force(&fa, (n + 255) / 256, mode, s));
   return SCF_OK;
 }
@@ -505,7 +513,7 @@ int gamma_units(const scf_plan* p, int64_t n, int64_t* stages) {
 // Adjoint workspace: the common layout (partials sized for both passes), the
 // segment's positions X_k and force weights W_k (k = 0..nsteps), the gamma
 // weights W', velocity and acceleration scratch, the Hessian-vector kernel's
-// block sums and the per-kick host sums S_k.
+// block sums of every kick and the per-kick host sums S_k.
 struct AdjLayout {
   WsLayout L;
   size_t X, Wsv, Wp, V, A, hp, S, total;
@@ -533,7 +541,7 @@ AdjLayout adj_layout(const scf_plan* p, int64_t n, int nsteps) {
   A.A = off;
   off += align256((size_t)3 * n * rs);
   A.hp = off;
-  off += align256((size_t)std::max<int64_t>(A.nblk, 1) * 32 * rs);
+  off += align256((size_t)(nsteps + 1) * std::max<int64_t>(A.nblk, 1) * 32 * rs);
   A.S = off;
   off += align256((size_t)(nsteps + 1) * 32 * sizeof(double));
   A.total = off;
@@ -1147,6 +1155,9 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
     fa.x = (Rt*)x;
     fa.y = (Rt*)y;
     fa.z = (Rt*)z;
+    fa.xo = (Rt*)x;
+    fa.yo = (Rt*)y;
+    fa.zo = (Rt*)z;
     fa.vx = (Rt*)vx;
     fa.vy = (Rt*)vy;
     fa.vz = (Rt*)vz;
@@ -1355,11 +1366,10 @@ scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* 
                             w, A.L, s);
         if (st != SCF_OK) return st;
         if (k == nsteps) break;
-        for (int c = 0; c < 3; ++c)
-          HIP_TRY(hipMemcpyAsync(Xk(k + 1, c), Xk(k, c), n * rs, hipMemcpyDeviceToDevice, s));
         row_of(k, row);
-        st = run_field<Rt>(p, n, Xk(k + 1, 0), Xk(k + 1, 1), Xk(k + 1, 2), Vb[0], Vb[1], Vb[2],
-                           Ab[0], Ab[1], Ab[2], nullptr, Wk(k), hp, row, 1, dt, dt, s);
+        st = run_field<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), Vb[0], Vb[1], Vb[2], Ab[0], Ab[1],
+                           Ab[2], nullptr, Wk(k), hp, row, 1, dt, dt, s, Xk(k + 1, 0),
+                           Xk(k + 1, 1), Xk(k + 1, 2));
         if (st != SCF_OK) return st;
       }
       // ---- reverse sweep over the kicks k = nsteps..0 ---------------------------
@@ -1392,23 +1402,23 @@ scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* 
         ha.cx = Rt(Rk[3 * k]);
         ha.cy = Rt(Rk[3 * k + 1]);
         ha.cz = Rt(Rk[3 * k + 2]);
-        ha.partials = (Rt*)(w + A.hp);
+        ha.partials = (Rt*)(w + A.hp) + (size_t)k * A.nblk * 32;
         {
           Timed t(p, s, K_ADJ);
           HIP_TRY(p->eng->launch_hvp(&ha, A.nblk, s));
         }
-        if (with_host)
-          HIP_TRY(launch_adj_reduce(p->dtype, w + A.hp, A.nblk, (double*)(w + A.S) + 32 * k, s));
-        // coefficient part: a' = -grad sum_t W'_t b_t at X_k, then lambda_x += m a'
-        st = run_field<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), nullptr, nullptr, nullptr, Ab[0],
-                           Ab[1], Ab[2], nullptr, w + A.Wp, none, nullptr, 0, 0.0, 0.0, s);
+        // coefficient part: lambda_x += m a' with a' = -grad sum_t W'_t b_t at X_k,
+        // then the reverse drift lambda_v += dt lambda_x (for k > 0)
+        st = run_field<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), lam[3], lam[4], lam[5], lam[0],
+                           lam[1], lam[2], nullptr, w + A.Wp, none, nullptr, 2, 0.0,
+                           k > 0 ? dt : 0.0, s, nullptr, nullptr, nullptr, m);
         if (st != SCF_OK) return st;
-        HIP_TRY(launch_adj_combine(p->dtype, n, m, Ab[0], Ab[1], Ab[2], lam[0], lam[1], lam[2],
-                                   lam[3], lam[4], lam[5], k > 0 ? dt : 0.0, s));
       }
-      if (with_host)
+      if (with_host) {
+        HIP_TRY(launch_adj_reduce(p->dtype, w + A.hp, A.nblk, nsteps + 1, (double*)(w + A.S), s));
         HIP_TRY(hipMemcpyAsync(S.data(), w + A.S, S.size() * sizeof(double),
                                hipMemcpyDeviceToHost, s));
+      }
     }
     HIP_TRY(hipStreamSynchronize(s));
     return SCF_OK;

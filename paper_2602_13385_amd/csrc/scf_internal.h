@@ -48,13 +48,17 @@ struct ForceArgs {
   R* x;
   R* y;
   R* z;
-  R* vx;
+  R* xo;  // step mode: drifted positions are written here (may equal x, y, z)
+  R* yo;
+  R* zo;
+  R* vx;  // adjoint mode: lambda_v
   R* vy;
   R* vz;
-  R* ax;
+  R* ax;  // adjoint mode: lambda_x
   R* ay;
   R* az;
   R* pot;
+  const R* mass;  // adjoint mode
   const R* W;         // [(lmax+1)^2][(NMAXC+1)] force weights, n fastest
   const R* beta_rad;  // as in CoefArgs
   const R* beta_ang;
@@ -114,7 +118,8 @@ struct Engine {
   virtual int max_resident_units(int v) const = 0;
   // launches variant v of the coefficient kernel over nunits wave-units
   virtual hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const = 0;
-  // launches the field kernel; mode 0 = forces, 1 = kick/drift step
+  // launches the field kernel; mode 0 = forces, 1 = kick/drift step,
+  // 2 = adjoint accumulation (lambda_x += m a, lambda_v += drift lambda_x)
   virtual hipError_t launch_force(const void* args, int64_t nblocks, int mode, hipStream_t s) const = 0;
   // adjoint: the gamma pass (coefficient kernel on dual positions, one
   // variant) and the Hessian-vector kernel
@@ -153,12 +158,9 @@ hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, i
                                    const double* centre_tab, int ncl, double* cur, int* step,
                                    hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
-// adjoint: lambda_x += m a', then lambda_v += drift lambda_x; and the
-// double-precision sum of the Hessian-vector kernel's 32 block sums
-hipError_t launch_adj_combine(int dtype, int64_t n, const void* m, const void* ax, const void* ay,
-                              const void* az, void* lx, void* ly, void* lz, void* lvx, void* lvy,
-                              void* lvz, double drift, hipStream_t s);
-hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, double* out,
-                             hipStream_t s);
+// adjoint: the double-precision sums of the Hessian-vector kernel's 32 block
+// sums, for nkicks kicks ([nkicks][nblocks][32] -> [nkicks][32])
+hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, int nkicks,
+                             double* out, hipStream_t s);
 
 }  // namespace scf

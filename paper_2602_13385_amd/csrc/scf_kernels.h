@@ -543,12 +543,12 @@ __global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
     ayv += gcy - hy;
     azv += gcz - hz;
   }
-  if (MODE == 0) {
+  if constexpr (MODE == 0) {
     a.ax[i] = axv;
     a.ay[i] = ayv;
     a.az[i] = azv;
     if (a.pot) a.pot[i] = psi;
-  } else {
+  } else if constexpr (MODE == 1) {
     R vx = fma(a.kick, axv, a.vx[i]);
     R vy = fma(a.kick, ayv, a.vy[i]);
     R vz = fma(a.kick, azv, a.vz[i]);
@@ -558,10 +558,24 @@ __global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
     a.ax[i] = axv;
     a.ay[i] = ayv;
     a.az[i] = azv;
+    if (a.drift != R(0) || a.xo != a.x) {
+      a.xo[i] = fma(a.drift, vx, x);
+      a.yo[i] = fma(a.drift, vy, y);
+      a.zo[i] = fma(a.drift, vz, z);
+    }
+  } else {
+    // adjoint: the coefficient part of a kick's vector-Jacobian product,
+    // lambda_x += m a (a from the gamma-weighted coefficients), then the
+    // reverse of the preceding drift, lambda_v += drift lambda_x
+    const R mi = a.mass[i];
+    const R lx = fma(mi, axv, a.ax[i]), ly = fma(mi, ayv, a.ay[i]), lz = fma(mi, azv, a.az[i]);
+    a.ax[i] = lx;
+    a.ay[i] = ly;
+    a.az[i] = lz;
     if (a.drift != R(0)) {
-      a.x[i] = fma(a.drift, vx, x);
-      a.y[i] = fma(a.drift, vy, y);
-      a.z[i] = fma(a.drift, vz, z);
+      a.vx[i] = fma(a.drift, lx, a.vx[i]);
+      a.vy[i] = fma(a.drift, ly, a.vy[i]);
+      a.vz[i] = fma(a.drift, lz, a.vz[i]);
     }
   }
 }
@@ -713,8 +727,10 @@ struct EngineImpl final : Engine {
       field_kernel<R, NMAXC, LMAX, 1, true><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
     else if (mode == 0)
       field_kernel<R, NMAXC, LMAX, 0, false><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
-    else
+    else if (mode == 1)
       field_kernel<R, NMAXC, LMAX, 1, false><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
+    else
+      field_kernel<R, NMAXC, LMAX, 2, false><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
     return hipGetLastError();
   }
   // adjoint gamma pass: variant 0's lane split on dual numbers

@@ -1,7 +1,7 @@
 // Small kernels of the SCF hot path that do not depend on (nmax, lmax): the
 // double-precision cross-block reductions of the coefficient sums, the force
 // weights, the standalone kick-drift, fills, the batched-mode reductions and
-// the adjoint's combination and reduction kernels; and the engine lookup.
+// the adjoint's reduction of its host sums; and the engine lookup.
 #include <hip/hip_runtime.h>
 
 #include "scf_internal.h"
@@ -30,26 +30,44 @@ __global__ void __launch_bounds__(256) reduce_kernel(const R* __restrict__ parti
     red1[(int64_t)blockIdx.y * T + t] = ((sh[0][ti] + sh[1][ti]) + sh[2][ti]) + sh[3][ti];
 }
 
+// a_t = cs_t * (sum of the chunk sums of t), in a fixed order (4 strided
+// chunk subsets, then their sum), and the force weights W[(l,j)][n] =
+// fw_t a_t; rows n in (nmax, nmaxc] of W are zero.
+template <typename R>
+__device__ __forceinline__ void finalize_block(const double* __restrict__ red1, int nchunks, int T,
+                                               int nmax, int lmax, int nmaxc,
+                                               const double* __restrict__ cs,
+                                               const double* __restrict__ fw, double* coef, R* W) {
+  __shared__ double sh[4][64];
+  const int L2 = (lmax + 1) * (lmax + 1);
+  const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + ti;
+  double s = 0.0;
+  if (t < T)
+    for (int c = kc; c < nchunks; c += 4) s += red1[(int64_t)c * T + t];
+  sh[kc][ti] = s;
+  __syncthreads();
+  if (kc == 0 && t < T) {
+    const double tot = ((sh[0][ti] + sh[1][ti]) + sh[2][ti]) + sh[3][ti];
+    const int n = t / L2, lj = t % L2;
+    const double cv = cs[t] * tot;
+    if (coef) coef[t] = cv;
+    W[lj * (nmaxc + 1) + n] = R(fw[t] * cv);
+  }
+  const int npad = (nmaxc - nmax) * L2;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npad; q += gridDim.x * blockDim.x) {
+    const int n = nmax + 1 + q / L2, lj = q % L2;
+    W[lj * (nmaxc + 1) + n] = R(0);
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ red1, int nchunks,
                                                        int T, int nmax, int lmax, int nmaxc,
                                                        const double* __restrict__ cs,
                                                        const double* __restrict__ fw, double* coef,
                                                        R* W) {
-  const int L2 = (lmax + 1) * (lmax + 1);
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // over (NMAXC+1) * L2 W entries
-  if (e >= (nmaxc + 1) * L2) return;
-  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
-  if (n > nmax) {
-    W[e] = R(0);
-    return;
-  }
-  const int t = n * L2 + lj;
-  double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += red1[(int64_t)c * T + t];
-  const double cv = cs[t] * s;
-  if (coef) coef[t] = cv;
-  W[e] = R(fw[t] * cv);
+  finalize_block<R>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw, coef, W);
 }
 
 template <typename R>
@@ -116,7 +134,6 @@ __global__ void __launch_bounds__(256) finalize_batched_kernel(
     const double* __restrict__ red1, int nchunks, int T, int nmax, int lmax, int nmaxc,
     const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W,
     int64_t W_stride, const double* __restrict__ centre_tab, int ncl, double* cur, int* step) {
-  const int L2 = (lmax + 1) * (lmax + 1);
   const int c = blockIdx.y;
   if (blockIdx.x == 0 && c == 0 && step) {
     const int k = *step;
@@ -125,21 +142,8 @@ __global__ void __launch_bounds__(256) finalize_batched_kernel(
     __syncthreads();
     if (threadIdx.x == 0) *step = k + 1;
   }
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (nmaxc + 1) * L2) return;
-  R* Wc = W + (int64_t)c * W_stride;
-  const int lj = e / (nmaxc + 1), n = e % (nmaxc + 1);
-  if (n > nmax) {
-    Wc[e] = R(0);
-    return;
-  }
-  const int t = n * L2 + lj;
-  const double* r = red1 + (int64_t)c * nchunks * T;
-  double s = 0.0;
-  for (int ch = 0; ch < nchunks; ++ch) s += r[(int64_t)ch * T + t];
-  const double cv = cs[t] * s;
-  if (coef) coef[(int64_t)c * T + t] = cv;
-  Wc[e] = R(fw[t] * cv);
+  finalize_block<R>(red1 + (int64_t)c * nchunks * T, nchunks, T, nmax, lmax, nmaxc, cs, fw,
+                    coef ? coef + (int64_t)c * T : nullptr, W + (int64_t)c * W_stride);
 }
 
 __global__ void set_int_kernel(int* p, int v) {
@@ -166,8 +170,7 @@ hipError_t launch_reduce(int dtype, const void* partials, int nblocks, int T, in
 hipError_t launch_finalize(int dtype, const double* red1, int nchunks, int T, int nmax, int lmax,
                            int nmaxc, const double* cs, const double* fw, double* coef, void* W,
                            hipStream_t s) {
-  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
-  const int grid = (ne + 255) / 256;
+  const int grid = (T + 63) / 64;
   if (dtype == 0)
     finalize_kernel<float><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw, coef,
                                                 (float*)W);
@@ -222,8 +225,7 @@ hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, i
                                    const double* centre_tab, int ncl, double* cur, int* step,
                                    hipStream_t s) {
   if (ncl <= 0) return hipSuccess;
-  const int ne = (nmaxc + 1) * (lmax + 1) * (lmax + 1);
-  dim3 grid((ne + 255) / 256, ncl);
+  dim3 grid((T + 63) / 64, ncl);
   if (dtype == 0)
     finalize_batched_kernel<float><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw,
                                                         coef, (float*)W, W_stride, centre_tab, ncl,
@@ -249,69 +251,33 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // adjoint helpers
 // ---------------------------------------------------------------------------
-// lambda_x += m a' (the coefficient part of the vector-Jacobian product, with
-// a' the field of the gamma-weighted coefficients), then, when drift != 0,
-// lambda_v += drift lambda_x (the reverse of the drift that precedes the kick)
-template <typename R>
-__global__ void __launch_bounds__(256) adj_combine_kernel(int64_t n, const R* __restrict__ m,
-                                                          const R* __restrict__ ax,
-                                                          const R* __restrict__ ay,
-                                                          const R* __restrict__ az, R* lx, R* ly,
-                                                          R* lz, R* lvx, R* lvy, R* lvz, R drift) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const R mi = m[i];
-  const R x = fma(mi, ax[i], lx[i]), y = fma(mi, ay[i], ly[i]), z = fma(mi, az[i], lz[i]);
-  lx[i] = x;
-  ly[i] = y;
-  lz[i] = z;
-  if (drift != R(0)) {
-    lvx[i] = fma(drift, x, lvx[i]);
-    lvy[i] = fma(drift, y, lvy[i]);
-    lvz[i] = fma(drift, z, lvz[i]);
-  }
-}
-
-// out[q] = sum over blocks of partials[b][q], q < 32, in double and in a fixed
-// order (8 strided block subsets, then their sum)
+// out[k][q] = sum over blocks b of partials[k][b][q], q < 32, for every kick
+// k (one block each), in double and in a fixed order (8 strided block
+// subsets, then their sum)
 template <typename R>
 __global__ void __launch_bounds__(256) adj_reduce_kernel(const R* __restrict__ partials,
                                                          int64_t nblocks, double* out) {
   __shared__ double sh[8][32];
   const int q = threadIdx.x & 31, part = threadIdx.x >> 5;
+  const R* pk = partials + (int64_t)blockIdx.x * nblocks * 32;
   double s = 0.0;
-  for (int64_t b = part; b < nblocks; b += 8) s += double(partials[b * 32 + q]);
+  for (int64_t b = part; b < nblocks; b += 8) s += double(pk[b * 32 + q]);
   sh[part][q] = s;
   __syncthreads();
   if (part == 0) {
     double t = 0.0;
     for (int k = 0; k < 8; ++k) t += sh[k][q];
-    out[q] = t;
+    out[(int64_t)blockIdx.x * 32 + q] = t;
   }
 }
 
-hipError_t launch_adj_combine(int dtype, int64_t n, const void* m, const void* ax, const void* ay,
-                              const void* az, void* lx, void* ly, void* lz, void* lvx, void* lvy,
-                              void* lvz, double drift, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((n + 255) / 256));
+hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, int nkicks,
+                             double* out, hipStream_t s) {
+  if (nkicks <= 0) return hipSuccess;
   if (dtype == 0)
-    adj_combine_kernel<float><<<grid, 256, 0, s>>>(
-        n, (const float*)m, (const float*)ax, (const float*)ay, (const float*)az, (float*)lx,
-        (float*)ly, (float*)lz, (float*)lvx, (float*)lvy, (float*)lvz, (float)drift);
+    adj_reduce_kernel<float><<<nkicks, 256, 0, s>>>((const float*)partials, nblocks, out);
   else
-    adj_combine_kernel<double><<<grid, 256, 0, s>>>(
-        n, (const double*)m, (const double*)ax, (const double*)ay, (const double*)az, (double*)lx,
-        (double*)ly, (double*)lz, (double*)lvx, (double*)lvy, (double*)lvz, drift);
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, double* out,
-                             hipStream_t s) {
-  if (dtype == 0)
-    adj_reduce_kernel<float><<<1, 256, 0, s>>>((const float*)partials, nblocks, out);
-  else
-    adj_reduce_kernel<double><<<1, 256, 0, s>>>((const double*)partials, nblocks, out);
+    adj_reduce_kernel<double><<<nkicks, 256, 0, s>>>((const double*)partials, nblocks, out);
   return hipGetLastError();
 }
 
