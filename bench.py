@@ -93,14 +93,17 @@ def run_main(dtype, steps, warmup, torch, scf, I, profile):
     if warmup:
         cen, acc = plan.step(st, m, w.dt, warmup, centre=cen, acc=acc)
     torch.cuda.synchronize()
-    if profile:
-        plan.profile(True)
-        plan.kernel_times()
     t0 = time.perf_counter()
     (cen, acc), ms = _timed(torch, lambda: plan.step(st, m, w.dt, steps, centre=cen, acc=acc))
     wall = time.perf_counter() - t0
-    kt = plan.kernel_times() if profile else {}
+    kt = {}
     if profile:
+        # per-kernel durations from HIP events around every launch, in a
+        # second run of the same length (the events are not in the timed run)
+        plan.profile(True)
+        plan.kernel_times()
+        cen, acc = plan.step(st, m, w.dt, steps, centre=cen, acc=acc)
+        kt = plan.kernel_times()
         plan.profile(False)
     return {"n": n, "T": plan.T, "nmax": w.nmax, "lmax": w.lmax, "ms": ms, "wall_s": wall,
             "kernels": kt, "dt": w.dt, "name": w.name, "variant": variant, "plan": plan,

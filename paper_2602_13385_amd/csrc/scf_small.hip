@@ -22,8 +22,10 @@ __global__ void __launch_bounds__(256) reduce_kernel(const R* __restrict__ parti
   int b1 = b0 + per_chunk;
   if (b1 > nblocks) b1 = nblocks;
   double s = 0.0;
-  if (t < T)
+  if (t < T) {
+#pragma unroll 8
     for (int b = b0 + kc; b < b1; b += 4) s += double(partials[(int64_t)b * T + t]);
+  }
   sh[kc][ti] = s;
   __syncthreads();
   if (kc == 0 && t < T)
@@ -37,11 +39,12 @@ template <typename R>
 __device__ __forceinline__ void finalize_block(const double* __restrict__ red1, int nchunks, int T,
                                                int nmax, int lmax, int nmaxc,
                                                const double* __restrict__ cs,
-                                               const double* __restrict__ fw, double* coef, R* W) {
+                                               const double* __restrict__ fw, double* coef, R* W,
+                                               int cb, int ncb) {
   __shared__ double sh[4][64];
   const int L2 = (lmax + 1) * (lmax + 1);
   const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
-  const int t = blockIdx.x * 64 + ti;
+  const int t = cb * 64 + ti;
   double s = 0.0;
   if (t < T)
     for (int c = kc; c < nchunks; c += 4) s += red1[(int64_t)c * T + t];
@@ -55,7 +58,7 @@ __device__ __forceinline__ void finalize_block(const double* __restrict__ red1, 
     W[lj * (nmaxc + 1) + n] = R(fw[t] * cv);
   }
   const int npad = (nmaxc - nmax) * L2;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npad; q += gridDim.x * blockDim.x) {
+  for (int q = cb * blockDim.x + threadIdx.x; q < npad; q += ncb * blockDim.x) {
     const int n = nmax + 1 + q / L2, lj = q % L2;
     W[lj * (nmaxc + 1) + n] = R(0);
   }
@@ -67,7 +70,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict_
                                                        const double* __restrict__ cs,
                                                        const double* __restrict__ fw, double* coef,
                                                        R* W) {
-  finalize_block<R>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw, coef, W);
+  finalize_block<R>(red1, nchunks, T, nmax, lmax, nmaxc, cs, fw, coef, W, blockIdx.x, gridDim.x);
 }
 
 template <typename R>
@@ -143,7 +146,8 @@ __global__ void __launch_bounds__(256) finalize_batched_kernel(
     if (threadIdx.x == 0) *step = k + 1;
   }
   finalize_block<R>(red1 + (int64_t)c * nchunks * T, nchunks, T, nmax, lmax, nmaxc, cs, fw,
-                    coef ? coef + (int64_t)c * T : nullptr, W + (int64_t)c * W_stride);
+                    coef ? coef + (int64_t)c * T : nullptr, W + (int64_t)c * W_stride, blockIdx.x,
+                    gridDim.x);
 }
 
 __global__ void set_int_kernel(int* p, int v) {
