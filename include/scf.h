@@ -202,6 +202,20 @@ const char* scf_plan_describe(const scf_plan* plan);
 scf_status scf_autotune(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
                         const void* m, void* ws, size_t ws_bytes, void* stream, double* best_ms);
 
+/* The field kernel has compiled variants too (register budget per thread:
+ * the compiler's own, or one that allows at least 4 waves per SIMD).
+ * scf_autotune_field computes the coefficients of the given particles, times
+ * each variant on the forces at those particles (written to ax, ay, az,
+ * device, caller-owned; synchronising the stream) and keeps the fastest for
+ * the plan; best_ms (nullable) receives its time.  The variants give bitwise
+ * identical results. */
+int32_t scf_plan_num_field_variants(const scf_plan* plan);
+int32_t scf_plan_field_variant(const scf_plan* plan);
+scf_status scf_plan_set_field_variant(scf_plan* plan, int32_t variant);
+scf_status scf_autotune_field(scf_plan* plan, int64_t n, const void* x, const void* y,
+                              const void* z, const void* m, void* ax, void* ay, void* az, void* ws,
+                              size_t ws_bytes, void* stream, double* best_ms);
+
 /* Kernel timing (tracing): when enabled, every kernel the plan launches is
  * bracketed by HIP events on its stream; scf_profile_read synchronises on
  * those events and returns, per kernel kind, the launch count and the summed

@@ -175,6 +175,7 @@ struct scf_plan {
   int amode;
   Engine* eng;
   int coef_variant = 0;
+  int field_variant = 0;
   int num_cu = 256;
   int resident[8] = {1, 1, 1, 1, 1, 1, 1, 1};  // resident wave-units per CU per variant
   int gamma_resident = 1;                        // same for the adjoint's gamma pass
@@ -491,7 +492,7 @@ scf_status run_field(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx
   fa.gcy = R(cen ? cen[4] : 0.0);
   fa.gcz = R(cen ? cen[5] : 0.0);
   Timed t(p, s, mode == 0 ? K_FIELD : (mode == 1 ? K_STEP_FIELD : K_ADJ));
-  HIP_TRY(p->eng->launch_force(&fa, (n + 255) / 256, mode, s));
+  HIP_TRY(p->eng->launch_force(&fa, (n + 255) / 256, mode, p->field_variant, s));
   return SCF_OK;
 }
 
@@ -671,6 +672,86 @@ scf_status scf_autotune(scf_plan* p, int64_t n, const void* x, const void* y, co
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   p->coef_variant = best;
+  p->prof = prof;
+  if (best_ms) *best_ms = bms / 3.0;
+  return SCF_OK;
+}
+
+int32_t scf_plan_num_field_variants(const scf_plan* p) { return p ? p->eng->field_variants() : 0; }
+
+int32_t scf_plan_field_variant(const scf_plan* p) { return p ? p->field_variant : -1; }
+
+scf_status scf_plan_set_field_variant(scf_plan* p, int32_t v) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (v < 0 || v >= p->eng->field_variants())
+    return fail(SCF_ERR_INVALID_ARG, "field variant %d outside [0, %d)", v, p->eng->field_variants());
+  p->field_variant = v;
+  return SCF_OK;
+}
+
+scf_status scf_autotune_field(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                              const void* m, void* ax, void* ay, void* az, void* ws,
+                              size_t ws_bytes, void* stream, double* best_ms) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (n <= 0) return SCF_OK;
+  if (!(x && y && z && m && ax && ay && az))
+    return fail(SCF_ERR_INVALID_ARG, "particle and output arrays must be non-null");
+  const size_t need = plain_need(p, n);
+  if (!ws || ws_bytes < need)
+    return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  const WsLayout L = ws_layout(p, n, 1, 0);
+  char* w = (char*)ws;
+  const bool prof = p->prof;
+  p->prof = false;
+  const int saved = p->field_variant;
+  scf_status st = p->dtype == SCF_F32
+                      ? run_coeffs<float>(p, n, x, y, z, m, (double*)(w + L.coef), w + L.W, w, L, s)
+                      : run_coeffs<double>(p, n, x, y, z, m, (double*)(w + L.coef), w + L.W, w, L, s);
+  if (st != SCF_OK) {
+    p->prof = prof;
+    return st;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = saved;
+  float bms = 1e30f;
+  for (int v = 0; v < p->eng->field_variants(); ++v) {
+    p->field_variant = v;
+    float tot = 0.f;
+    for (int rep = 0; rep < 4; ++rep) {
+      HIP_TRY(hipEventRecord(e0, s));
+      if (p->dtype == SCF_F32) {
+        HostParams<float> hp;
+        fill_host_params(hp, nullptr);
+        st = run_field<float>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, ax, ay,
+                              az, nullptr, w + L.W, hp, nullptr, 0, 0.0, 0.0, s);
+      } else {
+        HostParams<double> hp;
+        fill_host_params(hp, nullptr);
+        st = run_field<double>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, ax,
+                               ay, az, nullptr, w + L.W, hp, nullptr, 0, 0.0, 0.0, s);
+      }
+      if (st != SCF_OK) {
+        p->field_variant = saved;
+        p->prof = prof;
+        return st;
+      }
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tot += ms;
+    }
+    if (tot < bms) {
+      bms = tot;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->field_variant = best;
   p->prof = prof;
   if (best_ms) *best_ms = bms / 3.0;
   return SCF_OK;
@@ -1189,7 +1270,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
       ForceArgs<Rt> f2 = fa;
       f2.kick = Rt(kick);
       f2.drift = Rt(drift);
-      HIP_TRY(p->eng->launch_force(&f2, nblk, 1, q));
+      HIP_TRY(p->eng->launch_force(&f2, nblk, 1, p->field_variant, q));
       return SCF_OK;
     };
     scf_status st = upload_rows(acc_valid ? 1 : 0);
@@ -1219,6 +1300,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
       add(&nblk, sizeof(nblk));
       add(&nch, sizeof(nch));
       add(&v, sizeof(v));
+      add(&p->field_variant, sizeof(p->field_variant));
       add(&coef_int, sizeof(coef_int));
       if (!p->gexec || key != p->gkey) {
         if (p->gexec) HIP_TRY(hipGraphExecDestroy(p->gexec));

@@ -120,7 +120,10 @@ struct Engine {
   virtual hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const = 0;
   // launches the field kernel; mode 0 = forces, 1 = kick/drift step,
   // 2 = adjoint accumulation (lambda_x += m a, lambda_v += drift lambda_x)
-  virtual hipError_t launch_force(const void* args, int64_t nblocks, int mode, hipStream_t s) const = 0;
+  // field-kernel launch variants (register budget); fv < field_variants()
+  virtual int field_variants() const = 0;
+  virtual hipError_t launch_force(const void* args, int64_t nblocks, int mode, int fv,
+                                  hipStream_t s) const = 0;
   // adjoint: the gamma pass (coefficient kernel on dual positions, one
   // variant) and the Hessian-vector kernel
   virtual int gamma_stage_particles() const = 0;

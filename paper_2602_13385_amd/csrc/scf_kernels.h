@@ -508,8 +508,9 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
   }
 }
 
+// Body of the field kernel: one particle per thread of a 256-thread block.
 template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
-__global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
+__device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
   int64_t i;
   const R* __restrict__ W = a.W;
   R cx = a.cx, cy = a.cy, cz = a.cz, gcx = a.gcx, gcy = a.gcy, gcz = a.gcz;
@@ -578,6 +579,19 @@ __global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
       a.vz[i] = fma(a.drift, lz, a.vz[i]);
     }
   }
+}
+
+// Field kernel launch variants: the compiler's own register budget (at the
+// 256-thread block bound), or a budget for at least 4 waves per SIMD (fewer
+// registers, the Legendre state may go to scratch).  The autotuner picks.
+template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
+__global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
+  field_body<R, NMAXC, LMAX, MODE, BATCHED>(a);
+}
+template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+field_kernel_o4(ForceArgs<R> a) {
+  field_body<R, NMAXC, LMAX, MODE, BATCHED>(a);
 }
 
 // sum over the 64 lanes of a wave (every lane receives the total)
@@ -719,18 +733,29 @@ struct EngineImpl final : Engine {
       coef_kernel<R, NMAXC, LMAX, V::LPP[2], V::WPB[2]><<<nblocks, 64 * V::WPB[2], 0, s>>>(ca);
     return hipGetLastError();
   }
-  hipError_t launch_force(const void* args, int64_t nblocks, int mode,
+  int field_variants() const override { return 2; }
+  hipError_t launch_force(const void* args, int64_t nblocks, int mode, int fv,
                           hipStream_t s) const override {
     if (nblocks <= 0) return hipSuccess;
     const ForceArgs<R>& fa = *(const ForceArgs<R>*)args;
-    if (fa.blk_cluster)
-      field_kernel<R, NMAXC, LMAX, 1, true><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
-    else if (mode == 0)
-      field_kernel<R, NMAXC, LMAX, 0, false><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
-    else if (mode == 1)
-      field_kernel<R, NMAXC, LMAX, 1, false><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
-    else
-      field_kernel<R, NMAXC, LMAX, 2, false><<<dim3((unsigned)nblocks), 256, 0, s>>>(fa);
+    const dim3 g((unsigned)nblocks);
+    if (fv == 1 && mode != 2) {
+      if (fa.blk_cluster)
+        field_kernel_o4<R, NMAXC, LMAX, 1, true><<<g, 256, 0, s>>>(fa);
+      else if (mode == 0)
+        field_kernel_o4<R, NMAXC, LMAX, 0, false><<<g, 256, 0, s>>>(fa);
+      else
+        field_kernel_o4<R, NMAXC, LMAX, 1, false><<<g, 256, 0, s>>>(fa);
+    } else {
+      if (fa.blk_cluster)
+        field_kernel<R, NMAXC, LMAX, 1, true><<<g, 256, 0, s>>>(fa);
+      else if (mode == 0)
+        field_kernel<R, NMAXC, LMAX, 0, false><<<g, 256, 0, s>>>(fa);
+      else if (mode == 1)
+        field_kernel<R, NMAXC, LMAX, 1, false><<<g, 256, 0, s>>>(fa);
+      else
+        field_kernel<R, NMAXC, LMAX, 2, false><<<g, 256, 0, s>>>(fa);
+    }
     return hipGetLastError();
   }
   // adjoint gamma pass: variant 0's lane split on dual numbers

@@ -82,6 +82,11 @@ SIGNATURES = {
     "scf_plan_set_variant": (C.c_int, [_vp, C.c_int32]),
     "scf_plan_describe": (C.c_char_p, [_vp]),
     "scf_autotune": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _dp]),
+    "scf_plan_num_field_variants": (C.c_int32, [_vp]),
+    "scf_plan_field_variant": (C.c_int32, [_vp]),
+    "scf_plan_set_field_variant": (C.c_int, [_vp, C.c_int32]),
+    "scf_autotune_field": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                     C.c_size_t, _vp, _dp]),
     "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
     "scf_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -184,13 +189,34 @@ class Plan:
     def describe(self):
         return lib().scf_plan_describe(self._h).decode()
 
-    def autotune(self, x, y, z, m):
-        """Time the coefficient-kernel variants on these particles; keep the fastest."""
+    @property
+    def field_variant(self):
+        return int(lib().scf_plan_field_variant(self._h))
+
+    @field_variant.setter
+    def field_variant(self, v):
+        _check(lib().scf_plan_set_field_variant(self._h, int(v)))
+
+    @property
+    def num_field_variants(self):
+        return int(lib().scf_plan_num_field_variants(self._h))
+
+    def autotune(self, x, y, z, m, field=True):
+        """Time the coefficient-kernel variants (and, with field=True, the
+        field-kernel variants) on these particles; keep the fastest.
+        Returns (coefficient variant, its ms)."""
+        torch = _torch()
         self._check_arrays(x, y, z, m)
         ws = self.workspace(x.numel(), device=x.device)
         best = C.c_double(0.0)
         _check(lib().scf_autotune(self._h, x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(m), _ptr(ws),
                                   ws.numel(), _stream(), C.byref(best)))
+        if field:
+            a = [torch.empty_like(x) for _ in range(3)]
+            fbest = C.c_double(0.0)
+            _check(lib().scf_autotune_field(self._h, x.numel(), _ptr(x), _ptr(y), _ptr(z), _ptr(m),
+                                            *[_ptr(t) for t in a], _ptr(ws), ws.numel(), _stream(),
+                                            C.byref(fbest)))
         return self.variant, best.value
 
     def profile(self, enable=True):

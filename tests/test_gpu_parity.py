@@ -246,3 +246,23 @@ def test_step_matches_oracle(torch, S, O, case, dtype):
     out2 = np.stack([t.cpu().numpy() for t in st2]).astype(np.float64)
     split_tol = 1e-6 if dtype == "f32" else 1e-13
     assert np.abs(out2 - out).max() <= split_tol * np.abs(out).max()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_field_variants_are_bitwise_identical(torch, S, dtype):
+    p = I.hernquist(20_000, 4242)
+    plan = S.Plan(16, 10, dtype=dtype)
+    x, y, z = (_dev(torch, p.pos[i], dtype) for i in range(3))
+    m = _dev(torch, p.mass, dtype)
+    c = plan.coeffs(x, y, z, m)
+    outs = []
+    for v in range(plan.num_field_variants):
+        plan.field_variant = v
+        outs.append(plan.forces(x, y, z, c, host=([("nfw", (232.98, 20.0))], 1.0),
+                                centre=[20.0, 1.0, -2.0]))
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert torch.equal(a, b)
+    plan.autotune(x, y, z, m)
+    assert 0 <= plan.field_variant < plan.num_field_variants
