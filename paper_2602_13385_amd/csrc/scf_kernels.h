@@ -401,9 +401,10 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
     Er[m] = Er[m - 1] * g.ux - Ei[m - 1] * g.uy;
     Ei[m] = Er[m - 1] * g.uy + Ei[m - 1] * g.ux;
   }
-  R Qm1[L1], Qm2[L1], dQm1[L1], dQm2[L1];
+  // Legendre factors Qt_l^m of the two previous degrees, per order
+  R Qm1[L1], Qm2[L1];
 #pragma unroll
-  for (int m = 0; m <= LMAX; ++m) Qm1[m] = Qm2[m] = dQm1[m] = dQm2[m] = R(0);
+  for (int m = 0; m <= LMAX; ++m) Qm1[m] = Qm2[m] = R(0);
   psi = R(0);
   R psir = R(0), gx = R(0), gy = R(0), gz = R(0);
   R Gprev = R(0), Gl = g.g0;
@@ -432,25 +433,24 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
     }
     R psl = R(0), rhl = R(0), gxl = R(0), gyl = R(0), gzl = R(0);
     const Sc* __restrict__ Wl = W + l * l * NW;
-#pragma unroll
-    for (int m = 0; m <= LMAX; ++m) {
-      if (m > l) break;
-      R Q, dQ;
+    // Orders in descending order: the c-derivative of the monic-scaled factor
+    // is dQt_l^m/dc = (l - m) Qt_l^(m+1) (the next higher order of the same
+    // degree, already computed), so no derivative recurrence is carried.
+    R Qup = R(0);
+    auto order = [&](const int m) {
+      R Q;
       if (l == m) {
         Q = R(1);
-        dQ = R(0);
       } else if (l == m + 1) {
         Q = g.c;
-        dQ = R(1);
       } else {
         const Sc b = bA[m * L1 + l];
         Q = g.c * Qm1[m] - b * Qm2[m];
-        dQ = fma(g.c, dQm1[m], Qm1[m]) - b * dQm2[m];
       }
       Qm2[m] = Qm1[m];
       Qm1[m] = Q;
-      dQm2[m] = dQm1[m];
-      dQm1[m] = dQ;
+      const R dQ = Sc(l - m) * Qup;
+      Qup = Q;
       const Sc* __restrict__ wc = Wl + (m == 0 ? 0 : 2 * m - 1) * NW;
       R sc = R(wc[0]), dsc = R(0);
       if constexpr (NMAXC >= 1) {
@@ -489,6 +489,16 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
         gxl = fma(mQ, v3, gxl);
         gyl = fma(mQ, v4, gyl);
       }
+    };
+    // small degree ranges: the order loop is unrolled, so every register
+    // array is statically indexed; otherwise a compact runtime loop
+    if constexpr (LMAX <= 6) {
+#pragma unroll
+      for (int mr = 0; mr <= LMAX; ++mr)
+        if (LMAX - mr <= l) order(LMAX - mr);
+    } else {
+#pragma unroll 1
+      for (int m = l; m >= 0; --m) order(m);
     }
     psi = fma(Gl, psl, psi);
     psir = fma(dGl, psl, fma(Gl * g.dxi, rhl, psir));
