@@ -270,7 +270,7 @@ int coef_blocks_max(const scf_plan* p, int64_t n) {
   return nb;
 }
 
-constexpr int kReduceChunks = 64;
+constexpr int kReduceChunks = 32;
 
 struct WsLayout {
   size_t partials, red1, coef, W, total;

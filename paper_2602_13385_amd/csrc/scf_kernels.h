@@ -404,7 +404,9 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
   psi = R(0);
   R psir = R(0), gx = R(0), gy = R(0), gz = R(0);
   R Gprev = R(0), Gl = g.g0;
-  if constexpr (LMAX <= 6) {
+  // small degree ranges (and double precision, where the peeled form below
+  // needs more registers than two waves per SIMD allow): one degree at a time
+  if constexpr (LMAX <= 6 || sizeof(Sc) == 8) {
     // Legendre factors Qt_l^m of the two previous degrees, per order
     R Qm1[L1], Qm2[L1];
 #pragma unroll

@@ -46,8 +46,10 @@ __device__ __forceinline__ void finalize_block(const double* __restrict__ red1, 
   const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
   const int t = cb * 64 + ti;
   double s = 0.0;
-  if (t < T)
+  if (t < T) {
+#pragma unroll 8
     for (int c = kc; c < nchunks; c += 4) s += red1[(int64_t)c * T + t];
+  }
   sh[kc][ti] = s;
   __syncthreads();
   if (kc == 0 && t < T) {
