@@ -13,8 +13,10 @@ Also reported on the same JSON line: the FP64 path on the same workload, the
 batched path (10 Plummer progenitors in a composite host, one graph launch per
 step, against the summed plain per-cluster steps), the adjoint/forward time
 ratio of the checkpointed reverse pass (Plummer N = 1e5 in an NFW host, 2000
-steps, checkpoints every 100), the FP32 path's relative errors, and the FP64
-CPU oracle timed on a bounded sample.
+steps, checkpoints every 100), whole runs of the isolated Plummer (1e4
+particles, 100 steps) and of the Plummer in the logarithmic host (1e5
+particles, 1e4 steps) in FP32 and FP64, the FP32 path's relative errors, and
+the FP64 CPU oracle timed on a bounded sample.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -187,6 +189,64 @@ def run_batched(torch, scf, I, steps):
             "speedup_vs_plain": ms_plain / ms, "graph_captures": plan.graph_captures}
 
 
+def _energy(torch, plan, st, m):
+    """K + W in the cluster frame, W = 1/2 sum m psi_SCF (isolated cluster)."""
+    coef = plan.coeffs(st[0], st[1], st[2], m)
+    _, _, _, pot = plan.forces(st[0], st[1], st[2], coef, pot=True)
+    v2 = st[3].double() ** 2 + st[4].double() ** 2 + st[5].double() ** 2
+    md = m.double()
+    return float((0.5 * md * v2).sum() + 0.5 * (md * pot.double()).sum())
+
+
+def _lagrange_radii(torch, st, m, fracs=(0.1, 0.5, 0.9)):
+    r = (st[0].double() ** 2 + st[1].double() ** 2 + st[2].double() ** 2).sqrt()
+    order = torch.argsort(r)
+    cm = torch.cumsum(m.double()[order], 0)
+    cm = cm / cm[-1]
+    return [float(r[order][torch.searchsorted(cm, torch.tensor(f, dtype=torch.float64,
+                                                                   device=cm.device))])
+            for f in fracs]
+
+
+def run_long(torch, scf, I):
+    """The isolated Plummer (N = 1e4, 100 steps) and the Plummer in the log
+    host (N = 1e5, 1e4 steps): FP32 and FP64 step rates over the whole run,
+    energy conservation of the isolated cluster, and FP32-vs-FP64 agreement
+    of the final Lagrange radii (trajectories diverge particle by particle,
+    so the comparison is statistical)."""
+    out = {}
+    for w in (I.config1(), I.config2()):
+        p = w.clusters[0]
+        res = {}
+        for dtype in ("f32", "f64"):
+            td = torch.float32 if dtype == "f32" else torch.float64
+            st = [torch.as_tensor(p.state()[i], dtype=td, device="cuda").contiguous()
+                  for i in range(6)]
+            m = torch.as_tensor(p.mass, dtype=td, device="cuda")
+            plan = scf.Plan(w.nmax, w.lmax, dtype=dtype)
+            plan.autotune(st[0], st[1], st[2], m)
+            host = (w.host, w.G) if w.host else None
+            e0 = _energy(torch, plan, st, m) if not w.host else None
+            cen, acc = plan.step([t.clone() for t in st], m, w.dt, 2, host=host,
+                                 centre=w.centres[0])  # warm-up
+            (cen, acc), ms = _timed(torch, lambda: plan.step(st, m, w.dt, w.nsteps, host=host,
+                                                             centre=w.centres[0]))
+            r = {"ms_per_step": ms / w.nsteps,
+                 "value": p.n * plan.T * w.nsteps / (ms * 1e-3),
+                 "lagrange_radii_10_50_90": _lagrange_radii(torch, st, m)}
+            if e0 is not None:
+                e1 = _energy(torch, plan, st, m)
+                r["energy_rel_drift"] = (e1 - e0) / abs(e0)
+            res[dtype] = r
+        lr32 = res["f32"]["lagrange_radii_10_50_90"]
+        lr64 = res["f64"]["lagrange_radii_10_50_90"]
+        res["lagrange_radii_rel_diff_f32_vs_f64"] = [abs(a - b) / b for a, b in zip(lr32, lr64)]
+        res["steps"] = w.nsteps
+        res["N"] = p.n
+        out[w.name] = res
+    return out
+
+
 def run_adjoint(torch, scf, I, nsteps=None):
     """Plummer N = 1e5 in an NFW host, 2000 steps with checkpoints every 100:
     forward and backward times of the checkpointed autograd trajectory."""
@@ -356,6 +416,8 @@ def main():
         out["batched"] = run_batched(torch, scf, I, steps=50)
         print("[bench] adjoint", file=sys.stderr, flush=True)
         out["adjoint"] = run_adjoint(torch, scf, I)
+        print("[bench] long runs", file=sys.stderr, flush=True)
+        out["long_runs"] = run_long(torch, scf, I)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
