@@ -164,6 +164,9 @@ def run_batched(torch, scf, I, steps):
     cen, acc = plan.step_batched(off, st, m, w.dt, 3, host=host, centres=cens)
     (cen, acc), ms = _timed(torch, lambda: plan.step_batched(off, st, m, w.dt, steps, host=host,
                                                              centres=cen, acc=acc))
+    (cen, acc), ms_eager = _timed(torch, lambda: plan.step_batched(off, st, m, w.dt, steps,
+                                                                   host=host, centres=cen, acc=acc,
+                                                                   graph=False))
     # plain per-cluster steps on the same GPU, same particles
     parts = []
     for c in range(len(sizes)):
@@ -184,6 +187,7 @@ def run_batched(torch, scf, I, steps):
     T = plan.T
     return {"workload": w.name, "N_total": N, "clusters": len(sizes), "steps": steps,
             "value": N * T * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+            "no_graph_ms_per_step": ms_eager / steps,
             "plain_per_cluster_value": N * T * steps / (ms_plain * 1e-3),
             "plain_per_cluster_ms_per_step": ms_plain / steps,
             "speedup_vs_plain": ms_plain / ms, "graph_captures": plan.graph_captures}
@@ -294,6 +298,20 @@ def run_adjoint(torch, scf, I, nsteps=None):
             "dL_dcentre0": [float(v) for v in cen0.grad.numpy()],
             "timing": "wall clock around the autograd forward (checkpointed scf_step segments + "
                       "loss) and backward (scf_step_adjoint per segment, recompute included)"}
+
+
+def device_info(torch):
+    """Device name and, if rocm-smi answers, the current shader clock."""
+    import subprocess
+    info = {"name": torch.cuda.get_device_name(0)}
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
+        lines = [ln.strip() for ln in r.stdout.splitlines() if "sclk" in ln.lower()]
+        if lines:
+            info["sclk"] = lines[0]
+    except Exception:
+        pass
+    return info
 
 
 def cpu_baseline(nsample=1_000_000, reps=2):
@@ -423,6 +441,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline()
     else:
         out["cpu_baseline"] = None
+    out["device"] = device_info(torch)
     print(json.dumps(out))
 
 
