@@ -70,6 +70,9 @@ def lib():
         L.orc_field.argtypes = [C.POINTER(Basis), dp, C.c_int64, dp, dp, dp, dp, dp, dp, dp]
         L.orc_host_eval.argtypes = [C.POINTER(Host), dp, dp, dp, dp]
         L.orc_host_dgrad_dparam.argtypes = [C.POINTER(Host), dp, dp]
+        L.orc_power.argtypes = [C.c_int32, C.c_int32, dp, dp]
+        L.orc_tidal_norm.restype = C.c_double
+        L.orc_tidal_norm.argtypes = [C.POINTER(Host), dp]
         L.orc_step.restype = C.c_int
         L.orc_step.argtypes = [C.POINTER(Basis), C.POINTER(Host), C.c_int64, dp, dp, dp, dp, dp,
                                dp, dp, dp, C.c_double, C.c_int32, dp, dp]
@@ -193,6 +196,18 @@ def host_dgrad_dparam(H, pos):
     out = np.zeros(H.ncomp * 9)
     lib().orc_host_dgrad_dparam(C.byref(H), _p(pos), _p(out))
     return out.reshape(H.ncomp, 3, 3)
+
+
+def power(nmax, lmax, coef):
+    """E_l = sum_{n,m} |a_nlm|^2, l = 0..lmax."""
+    coef = _f64(coef)
+    El = np.zeros(lmax + 1)
+    lib().orc_power(int(nmax), int(lmax), _p(coef), _p(El))
+    return El
+
+
+def tidal_norm(H, pos):
+    return float(lib().orc_tidal_norm(C.byref(H), _p(_f64(np.asarray(pos, dtype=np.float64)))))
 
 
 def step(B, H, state, m, centre, dt, nsteps, want_acc=False):

@@ -701,6 +701,32 @@ int orc_step(const orc_basis* B, const orc_host* H, int64_t n, double* x, double
   return 0;
 }
 
+/* Power per degree (Sec. 3.5, Fig. power_spectrum_time_series):
+ * E_l = sum_n sum_{m=-l}^{l} |a_nlm|^2; with a_{nl,-m} = (-1)^m conj(a_nlm)
+ * this is sum_n [a_nl0^2 + 2 sum_{m>=1} (Re^2 + Im^2)]. */
+void orc_power(int32_t nmax, int32_t lmax, const double* coef, double* El) {
+  const int64_t L2 = (int64_t)(lmax + 1) * (lmax + 1);
+  for (int32_t l = 0; l <= lmax; ++l) {
+    double s = 0.0;
+    for (int32_t n = 0; n <= nmax; ++n)
+      for (int32_t j = 0; j <= 2 * l; ++j) {
+        const double a = coef[n * L2 + l * l + j];
+        s += (j == 0 ? 1.0 : 2.0) * a * a;
+      }
+    El[l] = s;
+  }
+}
+
+/* Frobenius norm of the host's tidal tensor T_ij = -d^2 psi_host / dx_i dx_j
+ * at pos (Sec. 2.2, Eq. tidal_tensor). */
+double orc_tidal_norm(const orc_host* H, const double* pos) {
+  double h[9];
+  orc_host_eval(H, pos, NULL, NULL, h);
+  double s = 0.0;
+  for (int i = 0; i < 9; ++i) s += h[i] * h[i];
+  return sqrt(s);
+}
+
 int orc_orbit(const orc_host* H, double* centre, double dt, int32_t nsteps, double* traj) {
   if (!centre || nsteps < 0) return 1;
   double* R = centre;

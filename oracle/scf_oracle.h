@@ -95,6 +95,12 @@ int orc_step(const orc_basis* B, const orc_host* H, int64_t n, double* x, double
              double* z, double* vx, double* vy, double* vz, const double* m,
              double* centre, double dt, int32_t nsteps, double* coef_last, double* acc);
 
+/* Power per degree E_l = sum_{n,m} |a_nlm|^2 (m = -l..l), l = 0..lmax. */
+void orc_power(int32_t nmax, int32_t lmax, const double* coef, double* El);
+
+/* Frobenius norm of the tidal tensor -Hess psi_host at pos. */
+double orc_tidal_norm(const orc_host* H, const double* pos);
+
 /* Test-particle (cluster-centre) orbit in the host alone, same leapfrog.
  * centre R,V updated in place; traj (may be NULL) receives (nsteps+1)*6. */
 int orc_orbit(const orc_host* H, double* centre, double dt, int32_t nsteps, double* traj);
