@@ -300,6 +300,35 @@ def run_adjoint(torch, scf, I, nsteps=None):
                       "loss) and backward (scf_step_adjoint per segment, recompute included)"}
 
 
+def run_diagnostics(torch, scf, I, chunks=10, per_chunk=200):
+    """Power per degree E_l(t) and the tidal-tensor norm ||T||(t) along the
+    eccentric orbit of the first progenitor of the batched workload, each
+    normalised by its initial value (the paper's power-spectrum time series)."""
+    w = I.config4()
+    p = w.clusters[0]
+    st = [torch.as_tensor(p.state()[i], dtype=torch.float32, device="cuda").contiguous()
+          for i in range(6)]
+    m = torch.as_tensor(p.mass, dtype=torch.float32, device="cuda")
+    plan = scf.Plan(w.nmax, w.lmax, dtype="f32")
+    host = (w.host, w.G)
+    coef = torch.empty(plan.T, dtype=torch.float64, device="cuda")
+    cen, acc = plan.step(st, m, w.dt, 0, host=host, centre=w.centres[0], coef_last=coef)
+    rows = []
+    for k in range(chunks + 1):
+        E = plan.power(coef).cpu().numpy()
+        rows.append({"t": k * per_chunk * w.dt, "E_l": [float(v) for v in E],
+                     "tidal_norm": scf.tidal_norm(host, cen[:3]), "R": float(sum(cen[:3] ** 2) ** 0.5)})
+        if k < chunks:
+            cen, acc = plan.step(st, m, w.dt, per_chunk, host=host, centre=cen, acc=acc,
+                                 coef_last=coef)
+    E0 = rows[0]["E_l"]
+    T0 = rows[0]["tidal_norm"]
+    return {"workload": f"{w.name} (cluster 0, N = {p.n})", "dt": w.dt,
+            "t": [r["t"] for r in rows], "R": [r["R"] for r in rows],
+            "E_l_over_initial": [[e / e0 for e, e0 in zip(r["E_l"], E0)] for r in rows],
+            "tidal_norm_over_initial": [r["tidal_norm"] / T0 for r in rows]}
+
+
 def device_info(torch):
     """Device name and, if rocm-smi answers, the current shader clock."""
     import subprocess
@@ -436,6 +465,8 @@ def main():
         out["adjoint"] = run_adjoint(torch, scf, I)
         print("[bench] long runs", file=sys.stderr, flush=True)
         out["long_runs"] = run_long(torch, scf, I)
+        print("[bench] diagnostics", file=sys.stderr, flush=True)
+        out["diagnostics"] = run_diagnostics(torch, scf, I)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -187,6 +187,19 @@ scf_status scf_step_adjoint(scf_plan* plan, int64_t n, const void* x0, const voi
 scf_status scf_adjoint_workspace_size(const scf_plan* plan, int64_t n, int32_t nsteps,
                                       size_t* bytes);
 
+/* Diagnostics (Sec. 3.5, Fig. power_spectrum_time_series).
+ * scf_power_spectrum: for each of ncoefsets coefficient vectors (device,
+ * ncoefsets*ncoef doubles, as written by the calls above) the power per
+ * degree E_l = sum_n sum_{m=-l..l} |a_nlm|^2 = sum_n [a_nl0^2 + 2 sum_{m>=1}
+ * (Re^2 + Im^2)] into power (device, ncoefsets*(lmax+1) doubles), on stream.
+ * sum_l E_l = -2 W with W = 1/2 sum_k m_k psi_SCF(x_k).
+ * scf_tidal_norm: the Frobenius norm of the host's tidal tensor
+ * T_ij = -d^2 psi_host / dx_i dx_j (Sec. 2.2, Eq. tidal_tensor) at pos[3]
+ * (host arrays, double precision, no device work). */
+scf_status scf_power_spectrum(scf_plan* plan, int32_t ncoefsets, const double* coef,
+                              double* power, void* stream);
+scf_status scf_tidal_norm(const scf_host* host, const double* pos, double* norm);
+
 /* Launch configuration.  The coefficient kernel has several compiled
  * variants (lanes per particle in the basis phase, waves per block).
  * scf_autotune times each on the given particles (synchronising the stream)

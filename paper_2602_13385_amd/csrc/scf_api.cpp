@@ -757,6 +757,33 @@ scf_status scf_autotune_field(scf_plan* p, int64_t n, const void* x, const void*
   return SCF_OK;
 }
 
+scf_status scf_power_spectrum(scf_plan* p, int32_t ncoefsets, const double* coef, double* power,
+                              void* stream) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (ncoefsets < 0) return fail(SCF_ERR_INVALID_ARG, "ncoefsets = %d < 0", ncoefsets);
+  if (ncoefsets == 0) return SCF_OK;
+  if (!coef || !power) return fail(SCF_ERR_INVALID_ARG, "coef and power must be non-null");
+  HIP_TRY(launch_power(coef, p->nmax, p->lmax, ncoefsets, power, (hipStream_t)stream));
+  return SCF_OK;
+}
+
+scf_status scf_tidal_norm(const scf_host* host, const double* pos, double* norm) {
+  if (!host || !pos || !norm) return fail(SCF_ERR_INVALID_ARG, "host, pos and norm must be non-null");
+  scf_status hs = check_host(host);
+  if (hs != SCF_OK) return hs;
+  HostParams<double> hd;
+  fill_host_params(hd, host);
+  double s = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double e[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0};
+    double h[3];
+    host_hess_vec<double>(hd, pos[0], pos[1], pos[2], e[0], e[1], e[2], h[0], h[1], h[2]);
+    s += h[0] * h[0] + h[1] * h[1] + h[2] * h[2];
+  }
+  *norm = std::sqrt(s);
+  return SCF_OK;
+}
+
 scf_status scf_profile_enable(scf_plan* p, int32_t enable) {
   if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
   if (enable && p->ev_pool.empty()) {

@@ -161,6 +161,9 @@ hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, i
                                    const double* centre_tab, int ncl, double* cur, int* step,
                                    hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
+// power per degree of ncl coefficient vectors (ncl x T in, ncl x (lmax+1) out)
+hipError_t launch_power(const double* coef, int nmax, int lmax, int ncl, double* El,
+                        hipStream_t s);
 // adjoint: the double-precision sums of the Hessian-vector kernel's 32 block
 // sums, for nkicks kicks ([nkicks][nblocks][32] -> [nkicks][32])
 hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, int nkicks,

@@ -287,6 +287,40 @@ hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, i
   return hipGetLastError();
 }
 
+// Power per degree: E_l = sum_n [a_nl0^2 + 2 sum_{m>=1} (Re^2 + Im^2)], one
+// block per degree, a fixed-order tree over the block.
+__global__ void __launch_bounds__(256) power_kernel(const double* __restrict__ coef, int nmax,
+                                                    int lmax, double* El) {
+  __shared__ double sh[256];
+  const int l = blockIdx.x;
+  const int L2 = (lmax + 1) * (lmax + 1);
+  const int per = 2 * l + 1;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < (nmax + 1) * per; q += blockDim.x) {
+    const int n = q / per, j = q % per;
+    const double a = coef[(int64_t)n * L2 + l * l + j];
+    s += (j == 0 ? 1.0 : 2.0) * a * a;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) El[l] = sh[0];
+}
+
+hipError_t launch_power(const double* coef, int nmax, int lmax, int ncl, double* El,
+                        hipStream_t s) {
+  const int64_t T = (int64_t)(nmax + 1) * (lmax + 1) * (lmax + 1);
+  for (int c = 0; c < ncl; ++c) {
+    power_kernel<<<lmax + 1, 256, 0, s>>>(coef + c * T, nmax, lmax, El + (int64_t)c * (lmax + 1));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 Engine* find_engine(int dtype, int nmax, int lmax) {
   if (nmax < 0 || lmax < 0) return nullptr;
   Engine* e = dtype == 0 ? find_engine_f32_exact(nmax, lmax) : find_engine_f64_exact(nmax, lmax);

@@ -87,6 +87,8 @@ SIGNATURES = {
     "scf_plan_set_field_variant": (C.c_int, [_vp, C.c_int32]),
     "scf_autotune_field": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                      C.c_size_t, _vp, _dp]),
+    "scf_power_spectrum": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
+    "scf_tidal_norm": (C.c_int, [C.POINTER(CHost), _dp, _dp]),
     "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
     "scf_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -148,6 +150,15 @@ def _ptr(t):
 def _stream():
     torch = _torch()
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def tidal_norm(host, pos):
+    """Frobenius norm of the host's tidal tensor at pos (3,), host = (components, G)."""
+    h = make_host(host[0], host[1])
+    p = (C.c_double * 3)(*[float(v) for v in pos[:3]])
+    out = C.c_double(0.0)
+    _check(lib().scf_tidal_norm(C.byref(h), C.cast(p, _dp), C.byref(out)))
+    return out.value
 
 
 class Plan:
@@ -321,6 +332,17 @@ class Plan:
                                       C.cast(lc, _dp), C.cast(gh, _dp), _ptr(ws), ws.numel(),
                                       _stream()))
         return np.array(lc[:]), np.array(gh[:3 * ncomp]).reshape(ncomp, 3)
+
+    def power(self, coef):
+        """E_l = sum_{n,m} |a_nlm|^2 of one coefficient vector (or of a batch,
+        shape (nclusters, ncoef)); returns a device tensor (..., lmax + 1)."""
+        torch = _torch()
+        c = coef.reshape(-1, self.T)
+        if c.dtype != torch.float64 or not c.is_cuda or not c.is_contiguous():
+            raise TypeError("expected a contiguous float64 CUDA tensor")
+        out = torch.empty(c.shape[0], self.lmax + 1, dtype=torch.float64, device=c.device)
+        _check(lib().scf_power_spectrum(self._h, c.shape[0], _ptr(c), _ptr(out), _stream()))
+        return out.reshape(*coef.shape[:-1], self.lmax + 1)
 
     @property
     def graph_captures(self):

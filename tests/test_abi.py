@@ -72,3 +72,13 @@ def test_null_pointers_rejected(S):
 def test_python_binding_has_no_cpu_fallback():
     src = open(os.path.join(ROOT, "paper_2602_13385_amd", "scf.py")).read()
     assert "oracle" not in src
+
+
+def test_tidal_norm_matches_oracle(S, O):
+    """scf_tidal_norm runs on the host (double precision, no device work)."""
+    comps = [("hernquist", (1.11955, 1.0)), ("mn", (11.8372, 3.0, 0.28)), ("nfw", (124.107, 15.626))]
+    H = O.host([(O.HOST_HERNQUIST, (1.11955, 1.0)), (O.HOST_MN, (11.8372, 3.0, 0.28)),
+                (O.HOST_NFW, (124.107, 15.626))])
+    for pos in ([20.0, 0.0, 0.0], [3.0, -4.0, 0.5], [0.2, 0.1, -8.0]):
+        ref = O.tidal_norm(H, pos)
+        assert S.tidal_norm((comps, 1.0), pos) == pytest.approx(ref, rel=1e-13)

@@ -266,3 +266,25 @@ def test_field_variants_are_bitwise_identical(torch, S, dtype):
             assert torch.equal(a, b)
     plan.autotune(x, y, z, m)
     assert 0 <= plan.field_variant < plan.num_field_variants
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_power_spectrum_matches_oracle(torch, S, O, dtype):
+    p = I.plummer(20_000, 77)
+    pos = _rounded(p.pos * np.array([[1.0], [0.8], [0.5]]), dtype)
+    m = _rounded(p.mass, dtype)
+    B = O.basis(10, 6)
+    ref = O.coeffs(B, *pos, m)
+    Eref = O.power(10, 6, ref)
+    plan = S.Plan(10, 6, dtype=dtype)
+    c = torch.as_tensor(_gpu_coeffs(torch, S, plan, pos, m, dtype), device="cuda")
+    E = plan.power(c).cpu().numpy()
+    # against the oracle: E_l = sum |a|^2 inherits twice the coefficient bar
+    assert np.abs(E - Eref).max() / Eref.max() <= 2 * TOL[dtype]
+    # the kernel's arithmetic, on the GPU's own coefficients
+    own = O.power(10, 6, c.cpu().numpy())
+    assert np.allclose(E, own, rtol=1e-13, atol=0)
+    # a batch of two coefficient sets
+    both = torch.stack([c, 2 * c])
+    Eb = plan.power(both).cpu().numpy()
+    assert np.allclose(Eb[0], own, rtol=1e-13) and np.allclose(Eb[1], 4 * own, rtol=1e-13)
