@@ -29,9 +29,10 @@
  *        j = 0 -> Re a_nl0;  j = 2m-1 -> Re a_nlm;  j = 2m -> Im a_nlm  (1<=m<=l),
  *    a_{nl,-m} = (-1)^m conj(a_nlm) being implied.
  *  - Device pointers are caller-owned (e.g. torch tensors).  The workspace is a
- *    caller-allocated device buffer of at least the size returned by the
- *    matching *_workspace_size query; the library allocates no device memory on
- *    these calls.  Host structs and host arrays are read (and, where stated,
+ *    caller-allocated, 256-byte-aligned device buffer of at least the size
+ *    returned by the matching *_workspace_size query; the library allocates no
+ *    device memory on these calls (plans allocate their small tables at
+ *    creation).  Output arrays must not alias input arrays unless stated.  Host structs and host arrays are read (and, where stated,
  *    written) during the call only.
  *  - stream is a hipStream_t (NULL = the null stream).  Calls enqueue work and
  *    return; device outputs are valid once the stream reaches that point.

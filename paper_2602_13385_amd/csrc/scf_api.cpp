@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -587,6 +588,9 @@ scf_status run_gamma(scf_plan* p, int64_t n, const void* x, const void* y, const
 
 bool ptr_ok(const void* q) { return q != nullptr; }
 
+// workspace regions are laid out at 256-byte offsets from its start
+bool ws_aligned(const void* ws) { return ((uintptr_t)ws & 255) == 0; }
+
 }  // namespace
 
 extern "C" {
@@ -637,6 +641,7 @@ scf_status scf_autotune(scf_plan* p, int64_t n, const void* x, const void* y, co
   const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  if (!ws_aligned(ws)) return fail(SCF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -699,6 +704,7 @@ scf_status scf_autotune_field(scf_plan* p, int64_t n, const void* x, const void*
   const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  if (!ws_aligned(ws)) return fail(SCF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   const WsLayout L = ws_layout(p, n, 1, 0);
   char* w = (char*)ws;
@@ -823,10 +829,12 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
   Engine* eng = find_engine(dtype, basis->nmax, basis->lmax);
   if (!eng)
     return fail(SCF_ERR_UNSUPPORTED, "no kernel for nmax = %d, lmax = %d", basis->nmax, basis->lmax);
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
   scf_plan* p = new scf_plan();
   p->basis = *basis;
   p->dtype = dtype;
-  HIP_TRY(hipGetDevice(&p->device));
+  p->device = device;
   p->nmax = basis->nmax;
   p->lmax = basis->lmax;
   p->nmaxc = eng->nmaxc();
@@ -930,6 +938,7 @@ scf_status scf_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
   const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  if (!ws_aligned(ws)) return fail(SCF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   const WsLayout L = ws_layout(p, n, 1, 0);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
@@ -953,6 +962,7 @@ scf_status scf_forces(scf_plan* p, int64_t n, const void* x, const void* y, cons
   const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  if (!ws_aligned(ws)) return fail(SCF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   const WsLayout L = ws_layout(p, n, 1, 0);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
@@ -1000,6 +1010,7 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
   const size_t need = plain_need(p, n);
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  if (!ws_aligned(ws)) return fail(SCF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   const WsLayout L = ws_layout(p, n, 1, 0);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
@@ -1094,6 +1105,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
   const BatchLayout B = batch_layout(p, n, ncl);
   if (!ws || ws_bytes < B.total)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", B.total, ws_bytes);
+  if (!ws_aligned(ws)) return fail(SCF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   const bool with_host = host && host->ncomp > 0;
@@ -1407,6 +1419,7 @@ scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* 
   const AdjLayout A = adj_layout(p, n, nsteps);
   if (!ws || ws_bytes < A.total)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", A.total, ws_bytes);
+  if (!ws_aligned(ws)) return fail(SCF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   if (nsteps == 0) return SCF_OK;  // the identity map
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
