@@ -23,7 +23,6 @@ Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time

@@ -110,9 +110,8 @@ struct Engine {
   virtual size_t real_size() const = 0;
   // coefficient-kernel variants (basis-phase lanes per particle, waves per block)
   virtual int coef_variants() const = 0;
-  // particles per wave-stage and waves per block of variant v
+  // particles per wave-stage of variant v
   virtual int stage_particles(int v) const = 0;
-  virtual int waves_per_block(int v) const = 0;
   // partial-sum rows written per wave-unit, and resident wave-units per CU
   virtual int rows_per_unit(int v) const = 0;
   virtual int max_resident_units(int v) const = 0;

@@ -847,7 +847,6 @@ struct EngineImpl final : Engine {
     if (e != hipSuccess || per_cu <= 0) per_cu = 1;
     return per_cu * V::WPB[v];
   }
-  int waves_per_block(int v) const override { return V::WPB[v]; }
   hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const override {
     if (nunits <= 0) return hipSuccess;
     const CoefArgs<R>& ca = *(const CoefArgs<R>*)args;
