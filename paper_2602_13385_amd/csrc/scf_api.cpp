@@ -408,6 +408,33 @@ void fill_coef_common(CoefArgs<R>& ca, const scf_plan* p) {
   ca.amode = p->amode;
 }
 
+// Sum of `rows` partial rows (FP32 or FP64) in double precision, then the
+// coefficients (coef, nullable) and force weights W.  Few rows: one pass;
+// otherwise chunk sums then their sum (two launches, fixed order either way).
+constexpr int kSmallRows = 512;
+
+scf_status reduce_and_finalize(scf_plan* p, const void* partials, int rows, double* coef, void* W,
+                               char* ws, const WsLayout& L, hipStream_t s) {
+  if (rows <= kSmallRows) {
+    Timed t(p, s, K_REDUCE);
+    HIP_TRY(launch_reduce_final_small(p->dtype, partials, rows, (int)p->T, p->nmax, p->lmax,
+                                      p->nmaxc, p->d_cs, p->d_fw, coef, W, s));
+    return SCF_OK;
+  }
+  double* red1 = (double*)(ws + L.red1);
+  const int nch = std::min(kReduceChunks, rows);
+  {
+    Timed t(p, s, K_REDUCE);
+    HIP_TRY(launch_reduce(p->dtype, partials, rows, (int)p->T, nch, red1, s));
+  }
+  {
+    Timed t(p, s, K_FINALIZE);
+    HIP_TRY(launch_finalize(p->dtype, red1, nch, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
+                            p->d_fw, coef, W, s));
+  }
+  return SCF_OK;
+}
+
 // coefficients of n particles into coef (device) and force weights W (device)
 template <typename R>
 scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
@@ -441,18 +468,7 @@ scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
     Timed t(p, s, K_COEF);
     HIP_TRY(p->eng->launch_coef(&ca, units, p->coef_variant, s));
   }
-  double* red1 = (double*)(ws + L.red1);
-  const int nch = std::min(kReduceChunks, nb);
-  {
-    Timed t(p, s, K_REDUCE);
-    HIP_TRY(launch_reduce(p->dtype, ca.partials, nb, (int)p->T, nch, red1, s));
-  }
-  {
-    Timed t(p, s, K_FINALIZE);
-    HIP_TRY(launch_finalize(p->dtype, red1, nch, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
-                            p->d_fw, coef, W, s));
-  }
-  return SCF_OK;
+  return reduce_and_finalize(p, ca.partials, nb, coef, W, ws, L, s);
 }
 
 // Field pass over n particles.  mode 0: a (and psi) into ax, ay, az (pot);
@@ -578,12 +594,7 @@ scf_status run_gamma(scf_plan* p, int64_t n, const void* x, const void* y, const
     HIP_TRY(p->eng->launch_gamma(&ca, units, s));
   }
   const int rows = units * p->eng->gamma_rows_per_unit();
-  const int nch = std::max(1, std::min(kReduceChunks, rows));
-  double* red1 = (double*)(ws + L.red1);
-  HIP_TRY(launch_reduce(p->dtype, ws + L.partials, rows, (int)p->T, nch, red1, s));
-  HIP_TRY(launch_finalize(p->dtype, red1, nch, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
-                          p->d_fw, nullptr, Wout, s));
-  return SCF_OK;
+  return reduce_and_finalize(p, ws + L.partials, rows, nullptr, Wout, ws, L, s);
 }
 
 bool ptr_ok(const void* q) { return q != nullptr; }

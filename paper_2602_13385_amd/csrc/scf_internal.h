@@ -145,6 +145,10 @@ hipError_t launch_reduce(int dtype, const void* partials, int nblocks, int T, in
 hipError_t launch_finalize(int dtype, const double* red1, int nchunks, int T, int nmax, int lmax,
                            int nmaxc, const double* cs, const double* fw, double* coef, void* W,
                            hipStream_t s);
+// launch_reduce + launch_finalize in one pass, for few partial rows
+hipError_t launch_reduce_final_small(int dtype, const void* partials, int nblocks, int T, int nmax,
+                                    int lmax, int nmaxc, const double* cs, const double* fw,
+                                    double* coef, void* W, hipStream_t s);
 hipError_t launch_make_w(int dtype, const double* coef, int T, int nmax, int lmax, int nmaxc,
                          const double* fw, void* W, hipStream_t s);
 hipError_t launch_kick_drift(int dtype, int64_t n, void* x, void* y, void* z, void* vx, void* vy,

@@ -380,9 +380,9 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
 // psi_SCF and a = -grad psi_SCF at one point (zero force at the origin).
 // R is float, double or Dual<T>; the tables (W, recurrence constants) are of
 // the scalar type.  The degree loop is a real (wave-uniform) loop so that only
-// one degree's radial vector is live; the order loop is unrolled with uniform
-// exits.
-template <typename R, int NMAXC, int LMAX>
+// one degree's radial vector is live.  PEEL selects the peeled order sweep
+// (below) for lmax > 6; otherwise one order loop per degree.
+template <typename R, int NMAXC, int LMAX, bool PEEL = (sizeof(scalar_t<R>) == 4)>
 __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
                                            const scalar_t<R>* __restrict__ W,
                                            const scalar_t<R>* __restrict__ bR,
@@ -406,7 +406,7 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
   R Gprev = R(0), Gl = g.g0;
   // small degree ranges (and double precision, where the peeled form below
   // needs more registers than two waves per SIMD allow): one degree at a time
-  if constexpr (LMAX <= 6 || sizeof(Sc) == 8) {
+  if constexpr (LMAX <= 6 || !PEEL) {
     // Legendre factors Qt_l^m of the two previous degrees, per order
     R Qm1[L1], Qm2[L1];
 #pragma unroll
@@ -637,7 +637,7 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
 }
 
 // Body of the field kernel: one particle per thread of a 256-thread block.
-template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
+template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED, bool PEEL>
 __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
   int64_t i;
   const R* __restrict__ W = a.W;
@@ -663,7 +663,7 @@ __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
   }
   const R x = a.x[i], y = a.y[i], z = a.z[i];
   R psi, axv, ayv, azv;
-  field_eval<R, NMAXC, LMAX>(x, y, z, W, a.beta_rad, a.beta_ang, a.binv, a.alpha, a.inv_alpha,
+  field_eval<R, NMAXC, LMAX, PEEL>(x, y, z, W, a.beta_rad, a.beta_ang, a.binv, a.alpha, a.inv_alpha,
                              a.amode, psi, axv, ayv, azv);
   if (a.host.ncomp > 0) {
     R hx, hy, hz;
@@ -710,16 +710,17 @@ __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
 }
 
 // Field kernel launch variants: the compiler's own register budget (at the
-// 256-thread block bound), or a budget for at least 4 waves per SIMD (fewer
-// registers, the Legendre state may go to scratch).  The autotuner picks.
+// 256-thread block bound; the peeled sweep in single precision, one order
+// loop per degree in double), or the peeled sweep under a budget for at least
+// 4 (single) or 2 (double) waves per SIMD.  The autotuner picks.
 template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
 __global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
-  field_body<R, NMAXC, LMAX, MODE, BATCHED>(a);
+  field_body<R, NMAXC, LMAX, MODE, BATCHED, sizeof(R) == 4>(a);
 }
 template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 field_kernel_o4(ForceArgs<R> a) {
-  field_body<R, NMAXC, LMAX, MODE, BATCHED>(a);
+  field_body<R, NMAXC, LMAX, MODE, BATCHED, true>(a);
 }
 
 // sum over the 64 lanes of a wave (every lane receives the total)

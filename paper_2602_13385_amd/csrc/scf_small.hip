@@ -66,6 +66,40 @@ __device__ __forceinline__ void finalize_block(const double* __restrict__ red1, 
   }
 }
 
+// Single-pass reduction for few partial rows: one block of 1024 threads per
+// 64 coefficients (16 row subsets, then their sum in a fixed order), then
+// the finalisation of those coefficients.
+template <typename R>
+__global__ void __launch_bounds__(1024) reduce_final_small_kernel(
+    const R* __restrict__ partials, int nblocks, int T, int nmax, int lmax, int nmaxc,
+    const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W) {
+  __shared__ double sh[16][64];
+  const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + ti;
+  double s = 0.0;
+  if (t < T) {
+#pragma unroll 8
+    for (int b = kc; b < nblocks; b += 16) s += double(partials[(int64_t)b * T + t]);
+  }
+  sh[kc][ti] = s;
+  __syncthreads();
+  const int L2 = (lmax + 1) * (lmax + 1);
+  if (kc == 0 && t < T) {
+    double tot = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tot += sh[k][ti];
+    const int n = t / L2, lj = t % L2;
+    const double cv = cs[t] * tot;
+    if (coef) coef[t] = cv;
+    W[lj * (nmaxc + 1) + n] = R(fw[t] * cv);
+  }
+  const int npad = (nmaxc - nmax) * L2;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npad; q += gridDim.x * blockDim.x) {
+    const int n = nmax + 1 + q / L2, lj = q % L2;
+    W[lj * (nmaxc + 1) + n] = R(0);
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ red1, int nchunks,
                                                        int T, int nmax, int lmax, int nmaxc,
@@ -170,6 +204,21 @@ hipError_t launch_reduce(int dtype, const void* partials, int nblocks, int T, in
     reduce_kernel<float><<<grid, 256, 0, s>>>((const float*)partials, nblocks, T, per_chunk, red1);
   else
     reduce_kernel<double><<<grid, 256, 0, s>>>((const double*)partials, nblocks, T, per_chunk, red1);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_final_small(int dtype, const void* partials, int nblocks, int T, int nmax,
+                                    int lmax, int nmaxc, const double* cs, const double* fw,
+                                    double* coef, void* W, hipStream_t s) {
+  if (T <= 0) return hipSuccess;
+  const int grid = (T + 63) / 64;
+  if (dtype == 0)
+    reduce_final_small_kernel<float><<<grid, 1024, 0, s>>>((const float*)partials, nblocks, T, nmax,
+                                                           lmax, nmaxc, cs, fw, coef, (float*)W);
+  else
+    reduce_final_small_kernel<double><<<grid, 1024, 0, s>>>((const double*)partials, nblocks, T,
+                                                            nmax, lmax, nmaxc, cs, fw, coef,
+                                                            (double*)W);
   return hipGetLastError();
 }
 
