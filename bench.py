@@ -329,16 +329,19 @@ def run_diagnostics(torch, scf, I, chunks=10, per_chunk=200):
 
 
 def device_info(torch):
-    """Device name and, if rocm-smi answers, the current shader clock."""
-    import subprocess
+    """Device name and the shader-clock levels the driver exposes in sysfs (the
+    active level is marked with '*'); read as files, no helper program runs."""
+    import glob
     info = {"name": torch.cuda.get_device_name(0)}
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
-        lines = [ln.strip() for ln in r.stdout.splitlines() if "sclk" in ln.lower()]
-        if lines:
-            info["sclk"] = lines[0]
-    except Exception:
-        pass
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            with open(path) as f:
+                levels = [ln.strip() for ln in f if ln.strip()]
+        except OSError:
+            continue
+        active = [ln for ln in levels if ln.endswith("*")]
+        info["sclk"] = active[0] if active else (levels[-1] if levels else None)
+        break
     return info
 
 

@@ -861,13 +861,16 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
     p->gamma_resident = eng->gamma_resident_units();
   }
   const int L1 = p->lmax + 1, NW = p->nmaxc + 1;
-  std::vector<double> brad((size_t)L1 * NW, 0.0), bang((size_t)L1 * L1, 0.0);
+  // Legendre table: b_{l,m} at [m L1 + l] (b_{m,m} = -1 starts the order
+  // recurrence of the field pass), then the integers 0..lmax at [L1 L1 + k]
+  std::vector<double> brad((size_t)L1 * NW, 0.0), bang((size_t)L1 * L1 + L1, 0.0);
   for (int l = 0; l <= p->lmax; ++l) {
     const double lam = (2.0 * l + 1.0) * basis->alpha + 0.5;
     for (int n = 0; n <= p->nmaxc; ++n) brad[(size_t)l * NW + n] = gegen_beta(n, lam);
   }
   for (int m = 0; m <= p->lmax; ++m)
-    for (int l = 0; l <= p->lmax; ++l) bang[(size_t)m * L1 + l] = legendre_gamma(l, m);
+    for (int l = 0; l <= p->lmax; ++l) bang[(size_t)m * L1 + l] = l == m ? -1.0 : legendre_gamma(l, m);
+  for (int k = 0; k <= p->lmax; ++k) bang[(size_t)L1 * L1 + k] = k;
   const int L2 = L1 * L1;
   p->h_cs.assign(p->T, 0.0);
   p->h_fw.assign(p->T, 0.0);

@@ -35,7 +35,7 @@ struct CoefArgs {
                              // takes stages [u*stages/nunits, (u+1)*stages/nunits)
   int nunits;                // number of wave-units (particle ranges)
   const S* beta_rad;         // [(lmax+1)][(NMAXC+1)]  monic Gegenbauer recurrence
-  const S* beta_ang;         // [(lmax+1)][(lmax+1)]   monic Legendre recurrence, [m][l]
+  const S* beta_ang;         // [(lmax+1)][(lmax+1)] monic Legendre recurrence [m][l], then 0..lmax
   acc_t<R>* partials;        // [nblocks][T]
   int T, nmax;
   S binv, alpha, inv_alpha;

@@ -380,9 +380,8 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
 // psi_SCF and a = -grad psi_SCF at one point (zero force at the origin).
 // R is float, double or Dual<T>; the tables (W, recurrence constants) are of
 // the scalar type.  The degree loop is a real (wave-uniform) loop so that only
-// one degree's radial vector is live.  PEEL selects the peeled order sweep
-// (below) for lmax > 6; otherwise one order loop per degree.
-template <typename R, int NMAXC, int LMAX, bool PEEL = (sizeof(scalar_t<R>) == 4)>
+// one degree's radial vector is live.
+template <typename R, int NMAXC, int LMAX>
 __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
                                            const scalar_t<R>* __restrict__ W,
                                            const scalar_t<R>* __restrict__ bR,
@@ -404,83 +403,76 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
   psi = R(0);
   R psir = R(0), gx = R(0), gy = R(0), gz = R(0);
   R Gprev = R(0), Gl = g.g0;
-  // small degree ranges (and double precision, where the peeled form below
-  // needs more registers than two waves per SIMD allow): one degree at a time
-  if constexpr (LMAX <= 6 || !PEEL) {
-    // Legendre factors Qt_l^m of the two previous degrees, per order
-    R Qm1[L1], Qm2[L1];
+  // Degrees in pairs: the Legendre factors of degree l overwrite those of
+  // degree l-2 (two arrays in ping-pong fashion), and the orders are a static
+  // sweep m = LMAX..0 that skips m > l, so every register array is statically
+  // indexed.  One recurrence covers every order m <= l: each array starts as 1
+  // at the indices of its own degree parity and 0 elsewhere, and the table
+  // holds b_{m,m} = -1, so entries that no degree has written yet give
+  // Qt_m^m = c 0 + 1 = 1 and Qt_{m+1}^m = c 1 - b 0 = c exactly.
+  R QA[L1], QB[L1];
 #pragma unroll
-    for (int m = 0; m <= LMAX; ++m) Qm1[m] = Qm2[m] = R(0);
-#pragma unroll 1
-    for (int l = 0; l <= LMAX; ++l) {
-      if (l > 0) {
-        Gprev = Gl;
-        Gl = Gl * g.w;
-      }
-      const Sc fl = Sc(l);
-      const R dGl = fl * Gprev * g.om - (Sc(2) * fl + Sc(1)) * g.kap * Gl;
-      // radial basis p_n and dp_n/dxi
-      R p[NW], dp[NW];
-      p[0] = R(1);
-      dp[0] = R(0);
+  for (int m = 0; m <= LMAX; ++m) {
+    QA[m] = R((m & 1) == 0 ? 1 : 0);
+    QB[m] = R((m & 1) == 1 ? 1 : 0);
+  }
+  auto degree = [&](const int l, R(&QW)[L1], const R(&QR)[L1]) {
+    if (l > 0) {
+      Gprev = Gl;
+      Gl = Gl * g.w;
+    }
+    const Sc fl = Sc(l);
+    const R dGl = fl * Gprev * g.om - (Sc(2) * fl + Sc(1)) * g.kap * Gl;
+    R p[NW], dp[NW];
+    p[0] = R(1);
+    dp[0] = R(0);
+    if constexpr (NMAXC >= 1) {
+      p[1] = g.xi;
+      dp[1] = R(1);
+    }
+    const Sc* __restrict__ bRl = bR + l * NW;
+#pragma unroll
+    for (int n = 2; n <= NMAXC; ++n) {
+      const Sc b = bRl[n];
+      p[n] = g.xi * p[n - 1] - b * p[n - 2];
+      dp[n] = fma(g.xi, dp[n - 1], p[n - 1]) - b * dp[n - 2];
+    }
+    R psl = R(0), rhl = R(0), gxl = R(0), gyl = R(0), gzl = R(0);
+    const Sc* __restrict__ Wl = W + l * l * NW;
+    const Sc* __restrict__ bl = bA + l;             // bl[m L1] = b_{l,m}
+    const Sc* __restrict__ kl = bA + L1 * L1 + l;   // kl[-m] = l - m
+    // sigma = sum_n W_n p_n and its xi-derivative for one (l, j) row
+    auto radial_sums = [&](const Sc* __restrict__ wc, R& sv, R& dv) {
+      sv = R(wc[0]);
+      dv = R(0);
       if constexpr (NMAXC >= 1) {
-        p[1] = g.xi;
-        dp[1] = R(1);
+        sv = fma(wc[1], p[1], sv);
+        dv = R(wc[1]);
       }
-      const Sc* __restrict__ bRl = bR + l * NW;
 #pragma unroll
       for (int n = 2; n <= NMAXC; ++n) {
-        const Sc b = bRl[n];
-        p[n] = g.xi * p[n - 1] - b * p[n - 2];
-        dp[n] = fma(g.xi, dp[n - 1], p[n - 1]) - b * dp[n - 2];
+        sv = fma(wc[n], p[n], sv);
+        dv = fma(wc[n], dp[n], dv);
       }
-      R psl = R(0), rhl = R(0), gxl = R(0), gyl = R(0), gzl = R(0);
-      const Sc* __restrict__ Wl = W + l * l * NW;
-      // Orders in descending order: the c-derivative of the monic-scaled factor
-      // is dQt_l^m/dc = (l - m) Qt_l^(m+1) (the next higher order of the same
-      // degree, already computed), so no derivative recurrence is carried.
-      R Qup = R(0);
-      auto order = [&](const int m) {
-        R Q;
-        if (l == m) {
-          Q = R(1);
-        } else if (l == m + 1) {
-          Q = g.c;
-        } else {
-          const Sc b = bA[m * L1 + l];
-          Q = g.c * Qm1[m] - b * Qm2[m];
-        }
-        Qm2[m] = Qm1[m];
-        Qm1[m] = Q;
-        const R dQ = Sc(l - m) * Qup;
+    };
+    R Qup = R(0);  // Qt_l^(m+1)
+#pragma unroll
+    for (int m = LMAX; m >= 0; --m) {
+      if (m <= l) {
+        const R Q = g.c * QR[m] - bl[m * L1] * QW[m];
+        QW[m] = Q;
+        const R dQ = kl[-m] * Qup;
         Qup = Q;
         const Sc* __restrict__ wc = Wl + (m == 0 ? 0 : 2 * m - 1) * NW;
-        R sc = R(wc[0]), dsc = R(0);
-        if constexpr (NMAXC >= 1) {
-          sc = fma(wc[1], p[1], sc);
-          dsc = R(wc[1]);
-        }
-#pragma unroll
-        for (int n = 2; n <= NMAXC; ++n) {
-          sc = fma(wc[n], p[n], sc);
-          dsc = fma(wc[n], dp[n], dsc);
-        }
+        R sc, dsc;
+        radial_sums(wc, sc, dsc);
         if (m == 0) {
           psl = fma(Q, sc, psl);
           rhl = fma(Q, dsc, rhl);
           gzl = fma(dQ, sc, gzl);
         } else {
-          const Sc* __restrict__ ws = wc + NW;
-          R ss = R(ws[0]), dss = R(0);
-          if constexpr (NMAXC >= 1) {
-            ss = fma(ws[1], p[1], ss);
-            dss = R(ws[1]);
-          }
-#pragma unroll
-          for (int n = 2; n <= NMAXC; ++n) {
-            ss = fma(ws[n], p[n], ss);
-            dss = fma(ws[n], dp[n], dss);
-          }
+          R ss, dss;
+          radial_sums(wc + NW, ss, dss);
           const R v1 = sc * Er[m] + ss * Ei[m];
           const R v2 = dsc * Er[m] + dss * Ei[m];
           const R v3 = sc * Er[m - 1] + ss * Ei[m - 1];
@@ -492,137 +484,18 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
           gxl = fma(mQ, v3, gxl);
           gyl = fma(mQ, v4, gyl);
         }
-      };
-      // small degree ranges: the order loop is unrolled, so every register
-      // array is statically indexed; otherwise a compact runtime loop
-      if constexpr (LMAX <= 6) {
-#pragma unroll
-        for (int mr = 0; mr <= LMAX; ++mr)
-          if (LMAX - mr <= l) order(LMAX - mr);
-      } else {
-#pragma unroll 1
-        for (int m = l; m >= 0; --m) order(m);
       }
-      psi = fma(Gl, psl, psi);
-      psir = fma(dGl, psl, fma(Gl * g.dxi, rhl, psir));
-      gx = fma(Gl, gxl, gx);
-      gy = fma(Gl, gyl, gy);
-      gz = fma(Gl, gzl, gz);
     }
-  } else {
-    // Large degree ranges: the orders are swept as a compact runtime loop.
-    // The Legendre factors of degree l overwrite those of degree l-2 (two
-    // arrays in ping-pong fashion, so one array store per order), the first
-    // two orders (Qt_l^l = 1, Qt_l^(l-1) = c) and the order 0 are peeled off
-    // the loop, and u^(m-1) is carried from one order to the next.
-    R QA[L1], QB[L1];
-#pragma unroll
-    for (int m = 0; m <= LMAX; ++m) QA[m] = QB[m] = R(0);
-    auto degree = [&](const int l, R(&QW)[L1], const R(&QR)[L1]) {
-      if (l > 0) {
-        Gprev = Gl;
-        Gl = Gl * g.w;
-      }
-      const Sc fl = Sc(l);
-      const R dGl = fl * Gprev * g.om - (Sc(2) * fl + Sc(1)) * g.kap * Gl;
-      R p[NW], dp[NW];
-      p[0] = R(1);
-      dp[0] = R(0);
-      if constexpr (NMAXC >= 1) {
-        p[1] = g.xi;
-        dp[1] = R(1);
-      }
-      const Sc* __restrict__ bRl = bR + l * NW;
-#pragma unroll
-      for (int n = 2; n <= NMAXC; ++n) {
-        const Sc b = bRl[n];
-        p[n] = g.xi * p[n - 1] - b * p[n - 2];
-        dp[n] = fma(g.xi, dp[n - 1], p[n - 1]) - b * dp[n - 2];
-      }
-      R psl = R(0), rhl = R(0), gxl = R(0), gyl = R(0), gzl = R(0);
-      const Sc* __restrict__ Wl = W + l * l * NW;
-      R Qup = R(0);           // Qt_l^(m+1)
-      R er = R(0), ei = R(0);  // u^m, carried down the orders
-      // sigma = sum_n W_n p_n and its xi-derivative for one (l, j) row
-      auto radial_sums = [&](const Sc* __restrict__ wc, R& sv, R& dv) {
-        sv = R(wc[0]);
-        dv = R(0);
-        if constexpr (NMAXC >= 1) {
-          sv = fma(wc[1], p[1], sv);
-          dv = R(wc[1]);
-        }
-#pragma unroll
-        for (int n = 2; n <= NMAXC; ++n) {
-          sv = fma(wc[n], p[n], sv);
-          dv = fma(wc[n], dp[n], dv);
-        }
-      };
-      // order m >= 1 with Legendre factor Q; er, ei hold u^m on entry
-      auto order = [&](const int m, const R Q) {
-        const R dQ = Sc(l - m) * Qup;
-        Qup = Q;
-        const Sc* __restrict__ wc = Wl + (2 * m - 1) * NW;
-        R sc, dsc, ss, dss;
-        radial_sums(wc, sc, dsc);
-        radial_sums(wc + NW, ss, dss);
-        const R er1 = Er[m - 1], ei1 = Ei[m - 1];
-        const R v1 = sc * er + ss * ei;
-        const R v2 = dsc * er + dss * ei;
-        const R v3 = sc * er1 + ss * ei1;
-        const R v4 = ss * er1 - sc * ei1;
-        const R mQ = Sc(m) * Q;
-        psl = fma(Q, v1, psl);
-        rhl = fma(Q, v2, rhl);
-        gzl = fma(dQ, v1, gzl);
-        gxl = fma(mQ, v3, gxl);
-        gyl = fma(mQ, v4, gyl);
-        er = er1;
-        ei = ei1;
-      };
-      auto order0 = [&](const R Q) {
-        const R dQ = fl * Qup;
-        R sc, dsc;
-        radial_sums(Wl, sc, dsc);
-        psl = fma(Q, sc, psl);
-        rhl = fma(Q, dsc, rhl);
-        gzl = fma(dQ, sc, gzl);
-      };
-      if (l == 0) {
-        QW[0] = R(1);
-        order0(R(1));
-      } else {
-        er = Er[l];
-        ei = Ei[l];
-        QW[l] = R(1);
-        order(l, R(1));
-        if (l == 1) {
-          QW[0] = g.c;
-          order0(g.c);
-        } else {
-          QW[l - 1] = g.c;
-          order(l - 1, g.c);
+    psi = fma(Gl, psl, psi);
+    psir = fma(dGl, psl, fma(Gl * g.dxi, rhl, psir));
+    gx = fma(Gl, gxl, gx);
+    gy = fma(Gl, gyl, gy);
+    gz = fma(Gl, gzl, gz);
+  };
 #pragma unroll 1
-          for (int m = l - 2; m >= 1; --m) {
-            const R Q = g.c * QR[m] - bA[m * L1 + l] * QW[m];
-            QW[m] = Q;
-            order(m, Q);
-          }
-          const R Q0 = g.c * QR[0] - bA[l] * QW[0];
-          QW[0] = Q0;
-          order0(Q0);
-        }
-      }
-      psi = fma(Gl, psl, psi);
-      psir = fma(dGl, psl, fma(Gl * g.dxi, rhl, psir));
-      gx = fma(Gl, gxl, gx);
-      gy = fma(Gl, gyl, gy);
-      gz = fma(Gl, gzl, gz);
-    };
-#pragma unroll 1
-    for (int l = 0; l <= LMAX; l += 2) {
-      degree(l, QA, QB);
-      if (l + 1 <= LMAX) degree(l + 1, QB, QA);
-    }
+  for (int l = 0; l <= LMAX; l += 2) {
+    degree(l, QA, QB);
+    if (l + 1 <= LMAX) degree(l + 1, QB, QA);
   }
   // grad psi = psi_r rhat + (1/r) (Gamma - (rhat . Gamma) rhat)
   const R rg = g.ux * gx + g.uy * gy + g.c * gz;
@@ -637,7 +510,7 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
 }
 
 // Body of the field kernel: one particle per thread of a 256-thread block.
-template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED, bool PEEL>
+template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
 __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
   int64_t i;
   const R* __restrict__ W = a.W;
@@ -663,7 +536,7 @@ __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
   }
   const R x = a.x[i], y = a.y[i], z = a.z[i];
   R psi, axv, ayv, azv;
-  field_eval<R, NMAXC, LMAX, PEEL>(x, y, z, W, a.beta_rad, a.beta_ang, a.binv, a.alpha, a.inv_alpha,
+  field_eval<R, NMAXC, LMAX>(x, y, z, W, a.beta_rad, a.beta_ang, a.binv, a.alpha, a.inv_alpha,
                              a.amode, psi, axv, ayv, azv);
   if (a.host.ncomp > 0) {
     R hx, hy, hz;
@@ -709,18 +582,17 @@ __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
   }
 }
 
-// Field kernel launch variants: the compiler's own register budget (at the
-// 256-thread block bound; the peeled sweep in single precision, one order
-// loop per degree in double), or the peeled sweep under a budget for at least
-// 4 (single) or 2 (double) waves per SIMD.  The autotuner picks.
+// Field kernel launch variants: the compiler's own register budget at the
+// 256-thread block bound, or a budget for at least 4 (single) or 2 (double)
+// waves per SIMD.  The autotuner picks.
 template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
 __global__ void __launch_bounds__(256) field_kernel(ForceArgs<R> a) {
-  field_body<R, NMAXC, LMAX, MODE, BATCHED, sizeof(R) == 4>(a);
+  field_body<R, NMAXC, LMAX, MODE, BATCHED>(a);
 }
 template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 field_kernel_o4(ForceArgs<R> a) {
-  field_body<R, NMAXC, LMAX, MODE, BATCHED, true>(a);
+  field_body<R, NMAXC, LMAX, MODE, BATCHED>(a);
 }
 
 // sum over the 64 lanes of a wave (every lane receives the total)
