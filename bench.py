@@ -329,8 +329,8 @@ def run_diagnostics(torch, scf, I, chunks=10, per_chunk=200):
 
 
 def device_info(torch):
-    """Device name and the shader-clock levels the driver exposes in sysfs (the
-    active level is marked with '*'); read as files, no helper program runs."""
+    """Device name and the shader-clock level the driver marks active in sysfs
+    at the time of the call (read as a file; no helper program runs)."""
     import glob
     info = {"name": torch.cuda.get_device_name(0)}
     for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
@@ -403,6 +403,7 @@ def main():
     scf.lib()
     print("[bench] headline FP32", file=sys.stderr, flush=True)
     r = run_main("f32", args.steps, args.warmup, torch, scf, I, profile=True)
+    dev = device_info(torch)  # the clock level right after the headline runs
     n, T = r["n"], r["T"]
     ms_per_step = r["ms"] / args.steps
     value = n * T * args.steps / (r["ms"] * 1e-3)
@@ -474,7 +475,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline()
     else:
         out["cpu_baseline"] = None
-    out["device"] = device_info(torch)
+    out["device"] = dev
     print(json.dumps(out))
 
 

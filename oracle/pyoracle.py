@@ -76,6 +76,9 @@ def lib():
         L.orc_step.restype = C.c_int
         L.orc_step.argtypes = [C.POINTER(Basis), C.POINTER(Host), C.c_int64, dp, dp, dp, dp, dp,
                                dp, dp, dp, C.c_double, C.c_int32, dp, dp]
+        L.orc_step_frozen.restype = C.c_int
+        L.orc_step_frozen.argtypes = [C.POINTER(Basis), C.POINTER(Host), C.c_int64, dp, dp, dp,
+                                      dp, dp, dp, dp, dp, C.c_double, C.c_int32]
         L.orc_orbit.restype = C.c_int
         L.orc_orbit.argtypes = [C.POINTER(Host), dp, C.c_double, C.c_int32, dp]
         L.orc_step_batched.restype = C.c_int
@@ -227,6 +230,19 @@ def step(B, H, state, m, centre, dt, nsteps, want_acc=False):
     if want_acc:
         return out, cen, coef, acc.reshape(3, n)
     return out, cen, coef
+
+
+def step_frozen(B, H, state, coef, centre, dt, nsteps):
+    """KDK steps in the frozen potential of coef (+ host differential field);
+    returns (state (6, n), centre (6,))."""
+    st = np.array(state, dtype=np.float64, copy=True)
+    rows = [np.ascontiguousarray(st[i]) for i in range(6)]
+    cen = _f64(np.array(centre, dtype=np.float64, copy=True))
+    rc = lib().orc_step_frozen(C.byref(B), C.byref(H) if H is not None else None, st.shape[1],
+                               *[_p(r) for r in rows], _p(_f64(coef)), _p(cen), float(dt),
+                               int(nsteps))
+    assert rc == 0
+    return np.stack(rows), cen
 
 
 def orbit(H, centre, dt, nsteps):

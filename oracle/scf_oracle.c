@@ -701,6 +701,70 @@ int orc_step(const orc_basis* B, const orc_host* H, int64_t n, double* x, double
   return 0;
 }
 
+/* Kick-drift-kick leapfrog in a frozen SCF potential (Sec. 2.2: between
+ * refreshes the particles move in the potential of fixed coefficients coef,
+ * plus the host's differential field about the centre, which follows the
+ * same leapfrog in the host alone). */
+static void accel_frozen(const orc_basis* B, const orc_host* H, int64_t n, const double* x,
+                         const double* y, const double* z, const double* coef, const double* R,
+                         double* ax, double* ay, double* az) {
+  if (n == 0) return;
+  orc_field(B, coef, n, x, y, z, NULL, ax, ay, az);
+  if (H && H->ncomp > 0) {
+    double g0[3];
+    orc_host_eval(H, R, NULL, g0, NULL);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+      double p[3] = {R[0] + x[k], R[1] + y[k], R[2] + z[k]}, g[3];
+      orc_host_eval(H, p, NULL, g, NULL);
+      ax[k] += -g[0] + g0[0];
+      ay[k] += -g[1] + g0[1];
+      az[k] += -g[2] + g0[2];
+    }
+  }
+}
+
+int orc_step_frozen(const orc_basis* B, const orc_host* H, int64_t n, double* x, double* y,
+                    double* z, double* vx, double* vy, double* vz, const double* coef,
+                    double* centre, double dt, int32_t nsteps) {
+  if (!B || n < 0 || nsteps < 0 || !centre || !coef) return 1;
+  double* ax = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+  double* ay = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+  double* az = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+  double* R = centre;
+  double* V = centre + 3;
+  double gc[3];
+  const double h = 0.5 * dt;
+  accel_frozen(B, H, n, x, y, z, coef, R, ax, ay, az);
+  centre_accel(H, R, gc);
+  for (int32_t s = 0; s < nsteps; ++s) {
+    for (int64_t k = 0; k < n; ++k) {
+      vx[k] += h * ax[k];
+      vy[k] += h * ay[k];
+      vz[k] += h * az[k];
+    }
+    for (int i = 0; i < 3; ++i) V[i] += h * gc[i];
+    for (int64_t k = 0; k < n; ++k) {
+      x[k] += dt * vx[k];
+      y[k] += dt * vy[k];
+      z[k] += dt * vz[k];
+    }
+    for (int i = 0; i < 3; ++i) R[i] += dt * V[i];
+    accel_frozen(B, H, n, x, y, z, coef, R, ax, ay, az);
+    centre_accel(H, R, gc);
+    for (int64_t k = 0; k < n; ++k) {
+      vx[k] += h * ax[k];
+      vy[k] += h * ay[k];
+      vz[k] += h * az[k];
+    }
+    for (int i = 0; i < 3; ++i) V[i] += h * gc[i];
+  }
+  free(ax);
+  free(ay);
+  free(az);
+  return 0;
+}
+
 /* Power per degree (Sec. 3.5, Fig. power_spectrum_time_series):
  * E_l = sum_n sum_{m=-l}^{l} |a_nlm|^2; with a_{nl,-m} = (-1)^m conj(a_nlm)
  * this is sum_n [a_nl0^2 + 2 sum_{m>=1} (Re^2 + Im^2)]. */

@@ -95,6 +95,13 @@ int orc_step(const orc_basis* B, const orc_host* H, int64_t n, double* x, double
              double* z, double* vx, double* vy, double* vz, const double* m,
              double* centre, double dt, int32_t nsteps, double* coef_last, double* acc);
 
+/* nsteps kick-drift-kick steps in the frozen SCF potential of coef plus the
+ * host's differential field (Sec. 2.2, between refreshes); the centre
+ * (R, V, in/out) follows the same leapfrog in the host alone. */
+int orc_step_frozen(const orc_basis* B, const orc_host* H, int64_t n, double* x, double* y,
+                    double* z, double* vx, double* vy, double* vz, const double* coef,
+                    double* centre, double dt, int32_t nsteps);
+
 /* Power per degree E_l = sum_{n,m} |a_nlm|^2 (m = -l..l), l = 0..lmax. */
 void orc_power(int32_t nmax, int32_t lmax, const double* coef, double* El);
 
