@@ -201,6 +201,114 @@ scf_status scf_power_spectrum(scf_plan* plan, int32_t ncoefsets, const double* c
                               double* power, void* stream);
 scf_status scf_tidal_norm(const scf_host* host, const double* pos, double* norm);
 
+/* ---- Refresh cadence (Sec. 2.2) ----------------------------------------
+ * Between refreshes the particles move in a frozen SCF potential.  The
+ * integration interval is Delta t_int = sqrt(eta) (|T|_F^2 / 6)^(-1/4)
+ * (Eq. tidal_timestep) with T the host tidal tensor (Eq. tidal_tensor) at the
+ * centre at the start of the interval; it is covered by ceil(Delta t_int /
+ * dt_max) equal kick-drift-kick substeps.  At its end the particles are
+ * selected in the potential they moved in: a particle is bound when
+ * |v|^2/2 + psi_SCF(x) < 0 (cluster frame; the paper's direct pair sum is
+ * replaced by psi_SCF, with the kinetic factor 1/2), r_x is the k-th smallest
+ * radius of the bound particles with k = ceil(x N_b) (an energy Lagrange
+ * radius), and only bound particles with r <= r_x enter the coefficient sum,
+ * with weight m (x = 0.999 in the paper).  Every refresh_every-th interval is
+ * a complete refresh: the coefficients of Eq. (sumanlm) over the selected
+ * particles.  The others are intermediate refreshes: the particles whose
+ * weight changed are added with weight w_new - w_old (recaptured: +m, lost:
+ * -m).  Orbit samples: N_s = max(1, ceil(n_s Delta t_int / t_dyn)) (capped by
+ * the substep count and ns_max), t_dyn = c_dyn sqrt(r_hm^3 / (G M_b)) with the
+ * bound mass M_b and r_hm = r_50 of the previous selection; sample j is the
+ * positions after substep ceil((j+1) nsub / N_s), and a refresh averages its
+ * sums over the samples.  Radii are compared through |x|^2 = (x x + y y) + z z
+ * with every operation rounded in the plan's precision. */
+#define SCF_MAX_SAMPLES 16
+typedef struct {
+  double eta;             /* Eq. tidal_timestep parameter (1/400 in the paper), > 0 */
+  double dt_max;          /* largest substep, > 0 */
+  double frac;            /* x of the selection radius r_x, in (0, 1] (0.999) */
+  double c_dyn;           /* t_dyn = c_dyn sqrt(r_hm^3 / (G M_b)); 2.91430 restates the
+                             paper's formula (4.3451 Myr at 1e5 Msun, 10 pc) for any units */
+  int32_t refresh_every;  /* complete refresh every this many intervals (5), >= 1 */
+  int32_t n_samples_tdyn; /* orbit samples per t_dyn (the paper: 1); 0: one sample at the end */
+  int32_t ns_max;         /* most samples per interval, 1..SCF_MAX_SAMPLES */
+  int32_t pad;
+} scf_cadence;
+
+/* Cadence state carried between calls (host, in/out). */
+typedef struct {
+  int32_t since;  /* intervals since the last complete refresh */
+  int32_t pad;
+  int64_t nbound; /* of the last selection: bound count N_b, */
+  double rx;      /* r_x, */
+  double rhm;     /* r_50, */
+  double mbound;  /* and bound mass M_b */
+} scf_cadence_state;
+
+/* One record per integration interval (host). */
+typedef struct {
+  double dt_int;          /* Delta t_int */
+  int32_t nsub, nsamples; /* substeps and orbit samples */
+  int32_t complete, pad;  /* 1: complete refresh, 0: intermediate */
+  int64_t nbound, nchanged; /* bound particles; particles whose weight changed */
+  double rx, rhm, mbound;
+} scf_interval_log;
+
+/* Workspace bytes for scf_select, scf_coeffs_delta, scf_cadence_init and
+ * scf_evolve on n particles keeping up to ns_max orbit samples. */
+scf_status scf_cadence_workspace_size(const scf_plan* plan, int64_t n, int32_t ns_max,
+                                      size_t* bytes);
+
+/* nsteps kick-drift-kick steps of size dt in the frozen potential of coef
+ * (device, ncoef doubles) plus the host's differential field; the centre
+ * (centre[6], host, in/out) follows the same leapfrog in the host alone, in
+ * double precision.  State and flags as for scf_step (ax, ay, az hold a(x)
+ * at the final positions on return). */
+scf_status scf_step_frozen(scf_plan* plan, int64_t n, void* x, void* y, void* z, void* vx,
+                           void* vy, void* vz, void* ax, void* ay, void* az, uint32_t step_flags,
+                           const double* coef, const scf_host* host, double* centre, double dt,
+                           int32_t nsteps, void* ws, size_t ws_bytes, void* stream);
+
+/* Selection in the potential of coef: w (device, n, plan dtype) receives
+ * m [bound and r <= r_frac], bound (device bytes, nullable) the bound flags,
+ * out (host) N_b, r_frac, r_50 and M_b (its since field is left as is).
+ * Blocks until out is written. */
+scf_status scf_select(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
+                      const void* vx, const void* vy, const void* vz, const void* m,
+                      const double* coef, double frac, void* w, uint8_t* bound,
+                      scf_cadence_state* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Intermediate refresh: coef (device, in/out) += (1/nsnap) sum_j
+ * a(snapshot j; w_new - w_old), the coefficients of Eq. (sumanlm) of the
+ * particles whose weight changed, at nsnap position snapshots (snaps: host
+ * array of 3*nsnap device pointers x_0, y_0, z_0, x_1, ...), 1 <= nsnap <=
+ * SCF_MAX_SAMPLES.  The changed particles are compacted first, so the cost
+ * follows their number, written to *nchanged (host).  Blocks until done. */
+scf_status scf_coeffs_delta(scf_plan* plan, int64_t n, int32_t nsnap, const void* const* snaps,
+                            const void* w_old, const void* w_new, double* coef, int64_t* nchanged,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Start of a cadence: the coefficients of all particles, the selection in
+ * their potential (fraction frac), and a complete refresh over the selected
+ * particles into coef (device); w (device) receives the weights and state
+ * (host) the selection, with since = 0.  Blocks. */
+scf_status scf_cadence_init(scf_plan* plan, int64_t n, const void* x, const void* y,
+                            const void* z, const void* vx, const void* vy, const void* vz,
+                            const void* m, double frac, double* coef, void* w,
+                            scf_cadence_state* state, void* ws, size_t ws_bytes, void* stream);
+
+/* nint integration intervals of the cadence from the state (x..vz, centre),
+ * the current coefficients coef (device, in/out), the current weights w
+ * (device, in/out) and the cadence state (host, in/out).  ax, ay, az are
+ * scratch (device, n each; a(x) in the last potential on return).  log
+ * (host, nullable) receives nint records.  Blocks once per interval (the
+ * selection's results come to the host). */
+scf_status scf_evolve(scf_plan* plan, int64_t n, void* x, void* y, void* z, void* vx, void* vy,
+                      void* vz, const void* m, void* ax, void* ay, void* az,
+                      const scf_host* host, double* centre, const scf_cadence* cadence,
+                      int32_t nint, double* coef, void* w, scf_cadence_state* state,
+                      scf_interval_log* log, void* ws, size_t ws_bytes, void* stream);
+
 /* Launch configuration.  The coefficient kernel has several compiled
  * variants (lanes per particle in the basis phase, waves per block).
  * scf_autotune times each on the given particles (synchronising the stream)
@@ -235,7 +343,7 @@ scf_status scf_autotune_field(scf_plan* plan, int64_t n, const void* x, const vo
  * those events and returns, per kernel kind, the launch count and the summed
  * event-to-event duration in milliseconds since the last read, then resets.
  * out must hold SCF_KERNEL_KINDS entries. */
-#define SCF_KERNEL_KINDS 12
+#define SCF_KERNEL_KINDS 13
 typedef struct {
   int32_t kind, count;
   double total_ms;

@@ -82,19 +82,38 @@ def energy_radius2(r2, bound, frac):
     return rb[k - 1], k, nb
 
 
+def rank_gap(r2, bound, k):
+    """Relative distance of the k-th smallest bound squared radius to its
+    neighbours (inf when it has none): how far the selection is from a tie."""
+    rb = np.sort(np.asarray(r2, dtype=np.float64)[np.asarray(bound, dtype=bool)])
+    if k < 1 or k > len(rb):
+        return np.inf
+    c = rb[k - 1]
+    g = np.inf
+    if k >= 2:
+        g = min(g, (c - rb[k - 2]) / c)
+    if k < len(rb):
+        g = min(g, (rb[k] - c) / c)
+    return g
+
+
 def select(B, coef, state, m, frac, key_dtype=np.float64):
     """Bound flags, selection weights w = m [bound and r <= r_x] and the
-    quantities the next interval needs (N_b, r_x, r_50, bound mass)."""
+    quantities the next interval needs (N_b, r_x, r_50, bound mass).  The info
+    also reports how close the decisions are to their thresholds: the smallest
+    |e| relative to the largest, and the rank gaps of r_x and r_50."""
     m = np.asarray(m, dtype=np.float64)
     e = specific_energy(B, coef, state)
     bound = e < 0.0
     r2 = squared_radii(state, key_dtype)
-    rx2, _, nb = energy_radius2(r2, bound, frac)
-    rh2, _, _ = energy_radius2(r2, bound, 0.5)
+    rx2, kx, nb = energy_radius2(r2, bound, frac)
+    rh2, kh, _ = energy_radius2(r2, bound, 0.5)
     w = np.where(bound & (r2 <= rx2), m, 0.0)
+    ae = np.abs(e)
     info = {"nbound": nb, "rx": math.sqrt(float(rx2)) if nb else 0.0,
             "rhm": math.sqrt(float(rh2)) if nb else 0.0, "mbound": float(m[bound].sum()),
-            "energy": e}
+            "energy": e, "emargin": float(ae.min() / ae.max()) if len(e) else np.inf,
+            "gap": min(rank_gap(r2, bound, kx), rank_gap(r2, bound, kh))}
     return w, bound, info
 
 
@@ -155,6 +174,8 @@ def evolve(B, H, state, m, centre, coef, w, nint, *, eta, dt_max, frac=0.999,
         nsub = max(1, int(math.ceil(dti / dt_max)))
         h = dti / nsub
         ns = min(n_samples(dti, mbound, rhm, n_samples_tdyn, c_dyn, B.G), nsub, ns_max)
+        ratio = (n_samples_tdyn * dti / (c_dyn * math.sqrt(rhm ** 3 / (B.G * mbound)))
+                 if n_samples_tdyn > 0 and mbound > 0.0 and rhm > 0.0 else 0.0)
         snaps, done = [], 0
         for end in sample_ends(nsub, ns):
             st, cen = O.step_frozen(B, H, st, coef, cen, h, end - done)
@@ -172,5 +193,6 @@ def evolve(B, H, state, m, centre, coef, w, nint, *, eta, dt_max, frac=0.999,
         mbound, rhm = info["mbound"], info["rhm"]
         log.append({"dt_int": dti, "nsub": nsub, "nsamples": ns, "kind": kind,
                     "nbound": info["nbound"], "nchanged": nchanged, "rx": info["rx"],
-                    "rhm": rhm, "mbound": mbound})
+                    "rhm": rhm, "mbound": mbound, "emargin": info["emargin"],
+                    "gap": info["gap"], "ns_ratio": ratio})
     return st, cen, coef, w, (since, mbound, rhm), log

@@ -172,4 +172,41 @@ hipError_t launch_power(const double* coef, int nmax, int lmax, int ncl, double*
 hipError_t launch_adj_reduce(int dtype, const void* partials, int64_t nblocks, int nkicks,
                              double* out, hipStream_t s);
 
+// ---- refresh cadence (selection and intermediate refresh) -----------------
+// State of the two-target radix selection (device): the selected key bits and
+// remaining ranks per target, the bound count, the ranks k_t and bound mass.
+struct SelectState {
+  uint64_t prefix[2];
+  int64_t rank[2];
+  int64_t k[2];
+  int64_t nb;
+  double mbound;
+  uint32_t hist[2][256];
+};
+constexpr int kMaxSamples = 16;  // orbit samples per interval (positions kept)
+struct DeltaSnaps {
+  int ns;
+  const void* x[kMaxSamples];
+  const void* y[kMaxSamples];
+  const void* z[kMaxSamples];
+};
+// bound flags (nullable) and squared-radius keys (u32 for FP32, u64 for FP64)
+hipError_t launch_energy_keys(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                              const void* vx, const void* vy, const void* vz, const void* pot,
+                              void* keys, uint8_t* bound, hipStream_t s);
+// the keys of ranks ceil(frac_t N_b), t = 0, 1, among the bound keys
+hipError_t launch_radix_select(int dtype, int64_t n, const void* keys, SelectState* st,
+                               double frac0, double frac1, int hist_blocks, hipStream_t s);
+// weights m [key <= selected key of target 0] and the bound mass
+hipError_t launch_select_weights(int dtype, int64_t n, const void* keys, const void* m,
+                                 SelectState* st, void* w, double* mass_part, hipStream_t s);
+// stable compaction of the particles with w0 != w1: positions of every
+// snapshot ([snapshot][x, y, z][cap]) and w1 - w0 ([cap]) into out (nullable:
+// count only); the count into *total
+hipError_t launch_delta_compact(int dtype, int64_t n, const void* w0, const void* w1,
+                                const DeltaSnaps& snaps, int32_t* cnt, int64_t* off,
+                                int64_t* total, void* out, int64_t cap, hipStream_t s);
+// y += a x on n doubles
+hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);
+
 }  // namespace scf

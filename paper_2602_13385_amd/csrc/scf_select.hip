@@ -1,0 +1,349 @@
+// Selection and refresh kernels of the refresh cadence (Sec. 2.2): the bound
+// test and squared-radius keys, an exact radix selection of the energy
+// Lagrange radii, the selection weights with the bound mass, the compaction
+// of the particles whose weight changed (intermediate refresh), and an FP64
+// axpy on coefficient vectors.  All HBM-bound, one pass each.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "scf_internal.h"
+
+namespace scf {
+namespace {
+
+template <typename R>
+struct KeyOf;
+template <>
+struct KeyOf<float> {
+  using K = uint32_t;
+  static __device__ __forceinline__ K bits(float v) { return __float_as_uint(v); }
+};
+template <>
+struct KeyOf<double> {
+  using K = uint64_t;
+  static __device__ __forceinline__ K bits(double v) { return (K)__double_as_longlong(v); }
+};
+
+// |v|^2/2 + psi < 0 marks a bound particle; its key is the bit pattern of
+// |x|^2 = ((x x + y y) + z z) with every operation rounded (a non-negative
+// float orders like its bits), unbound particles get the all-ones key.
+template <typename R>
+__global__ void __launch_bounds__(256) energy_keys_kernel(int64_t n, const R* __restrict__ x,
+                                                          const R* __restrict__ y,
+                                                          const R* __restrict__ z,
+                                                          const R* __restrict__ vx,
+                                                          const R* __restrict__ vy,
+                                                          const R* __restrict__ vz,
+                                                          const R* __restrict__ pot,
+                                                          typename KeyOf<R>::K* __restrict__ keys,
+                                                          uint8_t* __restrict__ bound) {
+#pragma clang fp contract(off)
+  using K = typename KeyOf<R>::K;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const R xi = x[i], yi = y[i], zi = z[i];
+  const R ux = vx[i], uy = vy[i], uz = vz[i];
+  const R e = R(0.5) * ((ux * ux + uy * uy) + uz * uz) + pot[i];
+  const bool b = e < R(0);
+  const R r2 = (xi * xi + yi * yi) + zi * zi;
+  keys[i] = b ? KeyOf<R>::bits(r2) : ~K(0);
+  if (bound) bound[i] = b ? 1 : 0;
+}
+
+// Histogram of one 8-bit digit (bits [shift, shift+8)) of the keys whose
+// higher bits equal each target's prefix, for two targets at once.
+template <typename K>
+__global__ void __launch_bounds__(256) radix_hist_kernel(int64_t n, const K* __restrict__ keys,
+                                                         SelectState* st, int shift, int first) {
+  __shared__ uint32_t h[2][256];
+  h[0][threadIdx.x] = 0;
+  h[1][threadIdx.x] = 0;
+  __syncthreads();
+  const int hs = shift + 8;
+  const K p0 = first ? K(0) : (K)st->prefix[0] >> hs;
+  const K p1 = first ? K(0) : (K)st->prefix[1] >> hs;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const K k = keys[i];
+    const unsigned d = (unsigned)(k >> shift) & 255u;
+    const K hi = hs >= (int)(8 * sizeof(K)) ? K(0) : k >> hs;
+    if (first || hi == p0) atomicAdd(&h[0][d], 1u);
+    if (first || hi == p1) atomicAdd(&h[1][d], 1u);
+  }
+  __syncthreads();
+  for (int t = 0; t < 2; ++t) {
+    const uint32_t c = h[t][threadIdx.x];
+    if (c) atomicAdd(&st->hist[t][threadIdx.x], c);
+  }
+}
+
+__global__ void __launch_bounds__(256) select_clear_kernel(SelectState* st) {
+  st->hist[0][threadIdx.x] = 0;
+  st->hist[1][threadIdx.x] = 0;
+  if (threadIdx.x < 2) {
+    st->prefix[threadIdx.x] = 0;
+    st->rank[threadIdx.x] = 0;
+    st->k[threadIdx.x] = 0;
+  }
+  if (threadIdx.x == 0) {
+    st->nb = 0;
+    st->mbound = 0.0;
+  }
+}
+
+// One block: picks each target's digit (the bucket that holds its remaining
+// rank), extends the prefix and clears the histograms for the next digit.
+// On the first digit it also derives the bound count (keys below all-ones)
+// and the ranks k_t = ceil(frac_t N_b), clamped to [1, N_b].
+__global__ void __launch_bounds__(256) radix_pick_kernel(SelectState* st, int shift, int first,
+                                                         int64_t n, double frac0, double frac1) {
+  __shared__ uint32_t cnt[256];
+  __shared__ int64_t scan[256];
+  const int tid = threadIdx.x;
+  if (first) {
+    if (tid == 0) {
+      const int64_t nb = n - (int64_t)st->hist[0][255];
+      st->nb = nb;
+      const double fr[2] = {frac0, frac1};
+      for (int t = 0; t < 2; ++t) {
+        int64_t k = nb > 0 ? (int64_t)ceil(fr[t] * (double)nb) : 0;
+        if (nb > 0) k = k < 1 ? 1 : (k > nb ? nb : k);
+        st->k[t] = k;
+        st->rank[t] = k > 0 ? k - 1 : 0;
+        st->prefix[t] = 0;
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = 0; t < 2; ++t) {
+    cnt[tid] = st->hist[t][tid];
+    __syncthreads();
+    if (tid == 0) {
+      int64_t c = 0;
+      for (int b = 0; b < 256; ++b) {
+        scan[b] = c;
+        c += cnt[b];
+      }
+    }
+    __syncthreads();
+    const int64_t r = st->rank[t];
+    const int64_t lo = scan[tid], hi = lo + cnt[tid];
+    __syncthreads();
+    if (st->nb > 0 && cnt[tid] > 0 && r >= lo && r < hi) {
+      st->prefix[t] |= (uint64_t)tid << shift;
+      st->rank[t] = r - lo;
+    }
+    __syncthreads();
+    st->hist[t][tid] = 0;
+    __syncthreads();
+  }
+}
+
+// w = m on bound particles with key <= the selected key, else 0; per-block
+// double sums of the bound mass (fixed order).
+template <typename R>
+__global__ void __launch_bounds__(256) select_weights_kernel(int64_t n,
+                                                             const typename KeyOf<R>::K* __restrict__ keys,
+                                                             const R* __restrict__ m,
+                                                             const SelectState* st,
+                                                             R* __restrict__ w,
+                                                             double* __restrict__ mass_part) {
+  using K = typename KeyOf<R>::K;
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double mb = 0.0;
+  if (i < n) {
+    const K k = keys[i];
+    const K kx = (K)st->prefix[0];
+    const R mi = m[i];
+    const bool b = k != ~K(0);
+    w[i] = (st->nb > 0 && b && k <= kx) ? mi : R(0);
+    if (b) mb = (double)mi;
+  }
+  red[threadIdx.x] = mb;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mass_part[blockIdx.x] = red[0];
+}
+
+// bound mass: the block sums added in a fixed order
+__global__ void __launch_bounds__(256) mass_sum_kernel(const double* __restrict__ part, int64_t nblk,
+                                                       SelectState* st) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += 256) s += part[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) st->mbound = red[0];
+}
+
+// ---- compaction of the particles whose weight changed ----------------------
+template <typename R>
+__global__ void __launch_bounds__(256) delta_count_kernel(int64_t n, const R* __restrict__ w0,
+                                                          const R* __restrict__ w1,
+                                                          int32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool f = i < n && w0[i] != w1[i];
+  const unsigned long long bal = __ballot(f);
+  __shared__ int32_t wc[4];
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+// exclusive scan of the block counts (one block of 1024 threads, each over a
+// contiguous chunk); total into *total
+__global__ void __launch_bounds__(1024) delta_scan_kernel(const int32_t* __restrict__ cnt,
+                                                          int64_t nblk, int64_t* __restrict__ off,
+                                                          int64_t* __restrict__ total) {
+  __shared__ int64_t part[1024];
+  const int64_t chunk = (nblk + 1023) / 1024;
+  const int64_t b0 = threadIdx.x * chunk;
+  const int64_t b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
+  int64_t s = 0;
+  for (int64_t b = b0; b < b1; ++b) s += cnt[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t c = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const int64_t v = part[t];
+      part[t] = c;
+      c += v;
+    }
+    *total = c;
+  }
+  __syncthreads();
+  int64_t c = part[threadIdx.x];
+  for (int64_t b = b0; b < b1; ++b) {
+    off[b] = c;
+    c += cnt[b];
+  }
+}
+
+// stable scatter of the changed particles: positions of every snapshot and
+// the weight change dw = w1 - w0
+template <typename R>
+__global__ void __launch_bounds__(256) delta_scatter_kernel(int64_t n, const R* __restrict__ w0,
+                                                            const R* __restrict__ w1,
+                                                            const int64_t* __restrict__ off,
+                                                            DeltaSnaps snaps, R* __restrict__ out,
+                                                            int64_t cap) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool f = i < n && w0[i] != w1[i];
+  const unsigned long long bal = __ballot(f);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ int32_t wc[4];
+  if (lane == 0) wc[wv] = __popcll(bal);
+  __syncthreads();
+  if (!f) return;
+  int32_t base = 0;
+  for (int q = 0; q < wv; ++q) base += wc[q];
+  const int32_t below = __popcll(bal & ((1ull << lane) - 1ull));
+  const int64_t o = off[blockIdx.x] + base + below;
+  // layout: [snapshot][x, y, z][cap], then dw[cap]
+  for (int j = 0; j < snaps.ns; ++j) {
+    R* dst = out + (int64_t)j * 3 * cap;
+    dst[o] = ((const R*)snaps.x[j])[i];
+    dst[cap + o] = ((const R*)snaps.y[j])[i];
+    dst[2 * cap + o] = ((const R*)snaps.z[j])[i];
+  }
+  out[(int64_t)snaps.ns * 3 * cap + o] = w1[i] - w0[i];
+}
+
+__global__ void __launch_bounds__(256) axpy_kernel(int64_t n, double a, const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+inline unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_energy_keys(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                              const void* vx, const void* vy, const void* vz, const void* pot,
+                              void* keys, uint8_t* bound, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (dtype == 0)
+    energy_keys_kernel<float><<<blocks_of(n), 256, 0, s>>>(
+        n, (const float*)x, (const float*)y, (const float*)z, (const float*)vx, (const float*)vy,
+        (const float*)vz, (const float*)pot, (uint32_t*)keys, bound);
+  else
+    energy_keys_kernel<double><<<blocks_of(n), 256, 0, s>>>(
+        n, (const double*)x, (const double*)y, (const double*)z, (const double*)vx,
+        (const double*)vy, (const double*)vz, (const double*)pot, (uint64_t*)keys, bound);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_select(int dtype, int64_t n, const void* keys, SelectState* st,
+                               double frac0, double frac1, int hist_blocks, hipStream_t s) {
+  const int kbits = dtype == 0 ? 32 : 64;
+  const unsigned g = (unsigned)(hist_blocks > 0 ? hist_blocks : 1);
+  select_clear_kernel<<<1, 256, 0, s>>>(st);
+  for (int shift = kbits - 8; shift >= 0; shift -= 8) {
+    const int first = shift == kbits - 8;
+    if (dtype == 0)
+      radix_hist_kernel<uint32_t><<<g, 256, 0, s>>>(n, (const uint32_t*)keys, st, shift, first);
+    else
+      radix_hist_kernel<uint64_t><<<g, 256, 0, s>>>(n, (const uint64_t*)keys, st, shift, first);
+    radix_pick_kernel<<<1, 256, 0, s>>>(st, shift, first, n, frac0, frac1);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_select_weights(int dtype, int64_t n, const void* keys, const void* m,
+                                 SelectState* st, void* w, double* mass_part, hipStream_t s) {
+  const int64_t nblk = n > 0 ? (int64_t)blocks_of(n) : 0;
+  if (n > 0) {
+    if (dtype == 0)
+      select_weights_kernel<float><<<blocks_of(n), 256, 0, s>>>(
+          n, (const uint32_t*)keys, (const float*)m, st, (float*)w, mass_part);
+    else
+      select_weights_kernel<double><<<blocks_of(n), 256, 0, s>>>(
+          n, (const uint64_t*)keys, (const double*)m, st, (double*)w, mass_part);
+  }
+  mass_sum_kernel<<<1, 256, 0, s>>>(mass_part, nblk, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_delta_compact(int dtype, int64_t n, const void* w0, const void* w1,
+                                const DeltaSnaps& snaps, int32_t* cnt, int64_t* off,
+                                int64_t* total, void* out, int64_t cap, hipStream_t s) {
+  const int64_t nblk = n > 0 ? (int64_t)blocks_of(n) : 0;
+  if (n > 0) {
+    if (dtype == 0)
+      delta_count_kernel<float><<<blocks_of(n), 256, 0, s>>>(n, (const float*)w0,
+                                                              (const float*)w1, cnt);
+    else
+      delta_count_kernel<double><<<blocks_of(n), 256, 0, s>>>(n, (const double*)w0,
+                                                               (const double*)w1, cnt);
+  }
+  delta_scan_kernel<<<1, 1024, 0, s>>>(cnt, nblk, off, total);
+  if (n > 0 && out) {
+    if (dtype == 0)
+      delta_scatter_kernel<float><<<blocks_of(n), 256, 0, s>>>(
+          n, (const float*)w0, (const float*)w1, off, snaps, (float*)out, cap);
+    else
+      delta_scatter_kernel<double><<<blocks_of(n), 256, 0, s>>>(
+          n, (const double*)w0, (const double*)w1, off, snaps, (double*)out, cap);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  axpy_kernel<<<blocks_of(n), 256, 0, s>>>(n, a, x, y);
+  return hipGetLastError();
+}
+
+}  // namespace scf

@@ -45,12 +45,56 @@ class CKernelTime(C.Structure):
     _fields_ = [("kind", C.c_int32), ("count", C.c_int32), ("total_ms", C.c_double)]
 
 
-KERNEL_KINDS = 12
+KERNEL_KINDS = 13
 
 
 class CHost(C.Structure):
     _fields_ = [("ncomp", C.c_int32), ("pad", C.c_int32), ("G", C.c_double),
                 ("comp", CHostComp * MAX_HOST_COMP)]
+
+
+class CCadence(C.Structure):
+    _fields_ = [("eta", C.c_double), ("dt_max", C.c_double), ("frac", C.c_double),
+                ("c_dyn", C.c_double), ("refresh_every", C.c_int32), ("n_samples_tdyn", C.c_int32),
+                ("ns_max", C.c_int32), ("pad", C.c_int32)]
+
+
+class CCadenceState(C.Structure):
+    _fields_ = [("since", C.c_int32), ("pad", C.c_int32), ("nbound", C.c_int64), ("rx", C.c_double),
+                ("rhm", C.c_double), ("mbound", C.c_double)]
+
+
+class CIntervalLog(C.Structure):
+    _fields_ = [("dt_int", C.c_double), ("nsub", C.c_int32), ("nsamples", C.c_int32),
+                ("complete", C.c_int32), ("pad", C.c_int32), ("nbound", C.c_int64),
+                ("nchanged", C.c_int64), ("rx", C.c_double), ("rhm", C.c_double),
+                ("mbound", C.c_double)]
+
+
+MAX_SAMPLES = 16
+# t_dyn = C_DYN sqrt(r_hm^3 / (G M)): the paper's 4.3451 Myr at 1e5 Msun and
+# 10 pc, with G = 4.30091727e-3 pc (km/s)^2 / Msun and 1 pc/(km/s) = 0.977792 Myr
+C_DYN = 4.3451 / ((1000.0 / (4.30091727e-3 * 1e5)) ** 0.5 * (3.0856775814913673e13 / 3.15576e13))
+
+
+@dataclass
+class Cadence:
+    """Parameters of the refresh cadence (include/scf.h, scf_cadence)."""
+    eta: float = 1.0 / 400.0
+    dt_max: float = 0.005
+    frac: float = 0.999
+    refresh_every: int = 5
+    n_samples_tdyn: int = 0
+    c_dyn: float = C_DYN
+    ns_max: int = 8
+
+    def c(self):
+        return CCadence(float(self.eta), float(self.dt_max), float(self.frac), float(self.c_dyn),
+                        int(self.refresh_every), int(self.n_samples_tdyn), int(self.ns_max), 0)
+
+
+def _state_dict(st):
+    return {"since": st.since, "nbound": st.nbound, "rx": st.rx, "rhm": st.rhm, "mbound": st.mbound}
 
 
 _lib = None
@@ -89,6 +133,20 @@ SIGNATURES = {
                                      C.c_size_t, _vp, _dp]),
     "scf_power_spectrum": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "scf_tidal_norm": (C.c_int, [C.POINTER(CHost), _dp, _dp]),
+    "scf_cadence_workspace_size": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scf_step_frozen": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  C.c_uint32, _vp, C.POINTER(CHost), _dp, C.c_double, C.c_int32,
+                                  _vp, C.c_size_t, _vp]),
+    "scf_select": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double,
+                             _vp, _vp, C.POINTER(CCadenceState), _vp, C.c_size_t, _vp]),
+    "scf_coeffs_delta": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(_vp), _vp, _vp, _vp,
+                                   C.POINTER(C.c_int64), _vp, C.c_size_t, _vp]),
+    "scf_cadence_init": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double,
+                                   _vp, _vp, C.POINTER(CCadenceState), _vp, C.c_size_t, _vp]),
+    "scf_evolve": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                             C.POINTER(CHost), _dp, C.POINTER(CCadence), C.c_int32, _vp, _vp,
+                             C.POINTER(CCadenceState), C.POINTER(CIntervalLog), _vp, C.c_size_t,
+                             _vp]),
     "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
     "scf_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -374,3 +432,103 @@ class Plan:
                                       cen.ctypes.data_as(_dp), float(dt), int(nsteps),
                                       _ptr(coef_last), _ptr(ws), ws.numel(), _stream()))
         return cen, acc
+
+    # ---- refresh cadence (Sec. 2.2) -----------------------------------------
+    def cadence_workspace(self, n, ns_max=1, device=None):
+        torch = _torch()
+        need = C.c_size_t()
+        _check(lib().scf_cadence_workspace_size(self._h, int(n), int(ns_max), C.byref(need)))
+        if self._ws is None or self._ws.numel() < need.value:
+            self._ws = torch.empty(max(need.value, 256), dtype=torch.uint8,
+                                   device=device or torch.device("cuda"))
+        return self._ws
+
+    def step_frozen(self, st, coef, dt, nsteps, host=None, centre=None, acc=None):
+        """Advance st = [x, y, z, vx, vy, vz] in place in the frozen potential
+        of coef (+ the host's differential field).  Returns (centre, acc)."""
+        torch = _torch()
+        self._check_arrays(*st)
+        n = st[0].numel()
+        acc_valid = acc is not None
+        if acc is None:
+            acc = [torch.empty_like(st[0]) for _ in range(3)]
+        cen = (C.c_double * 6)(*[float(v) for v in (centre if centre is not None else np.zeros(6))])
+        h = make_host(host[0], host[1]) if host is not None else None
+        ws = self.workspace(n, device=st[0].device)
+        _check(lib().scf_step_frozen(self._h, n, *[_ptr(t) for t in st], *[_ptr(t) for t in acc],
+                                     STEP_ACC_VALID if acc_valid else 0, _ptr(coef),
+                                     C.byref(h) if h is not None else None, C.cast(cen, _dp),
+                                     float(dt), int(nsteps), _ptr(ws), ws.numel(), _stream()))
+        return np.array(cen[:]), acc
+
+    def select(self, st, m, coef, frac=0.999, bound=False):
+        """Selection in the potential of coef: returns (w, bound flags or None,
+        {nbound, rx, rhm, mbound})."""
+        torch = _torch()
+        self._check_arrays(*st, m)
+        n = st[0].numel()
+        w = torch.empty_like(m)
+        b = torch.empty(n, dtype=torch.uint8, device=m.device) if bound else None
+        out = CCadenceState()
+        ws = self.cadence_workspace(n, 1, device=m.device)
+        _check(lib().scf_select(self._h, n, *[_ptr(t) for t in st], _ptr(m), _ptr(coef),
+                                float(frac), _ptr(w), _ptr(b), C.byref(out), _ptr(ws), ws.numel(),
+                                _stream()))
+        d = _state_dict(out)
+        del d["since"]
+        return w, b, d
+
+    def coeffs_delta(self, snaps, w_old, w_new, coef):
+        """coef += mean over snapshots [(x, y, z), ...] of the coefficients of
+        the particles whose weight changed, weights w_new - w_old (in place).
+        Returns the number of changed particles."""
+        flat = [t for xyz in snaps for t in xyz]
+        self._check_arrays(*flat, w_old, w_new)
+        n = w_old.numel()
+        arr = (C.c_void_p * len(flat))(*[t.data_ptr() for t in flat])
+        nch = C.c_int64()
+        ws = self.cadence_workspace(n, len(snaps), device=w_old.device)
+        _check(lib().scf_coeffs_delta(self._h, n, len(snaps), C.cast(arr, C.POINTER(C.c_void_p)),
+                                      _ptr(w_old), _ptr(w_new), _ptr(coef), C.byref(nch), _ptr(ws),
+                                      ws.numel(), _stream()))
+        return int(nch.value)
+
+    def cadence_init(self, st, m, frac=0.999):
+        """Start of a cadence: returns (coef, w, state dict)."""
+        torch = _torch()
+        self._check_arrays(*st, m)
+        n = st[0].numel()
+        coef = torch.empty(self.T, dtype=torch.float64, device=m.device)
+        w = torch.empty_like(m)
+        cs = CCadenceState()
+        ws = self.cadence_workspace(n, 1, device=m.device)
+        _check(lib().scf_cadence_init(self._h, n, *[_ptr(t) for t in st], _ptr(m), float(frac),
+                                      _ptr(coef), _ptr(w), C.byref(cs), _ptr(ws), ws.numel(),
+                                      _stream()))
+        return coef, w, _state_dict(cs)
+
+    def evolve(self, st, m, nint, cadence, host, centre, coef, w, state, acc=None):
+        """nint intervals of the cadence; st, coef and w are updated in place.
+        Returns (centre (6,), state dict, log list of dicts)."""
+        torch = _torch()
+        self._check_arrays(*st, m, w)
+        n = st[0].numel()
+        if acc is None:
+            acc = [torch.empty_like(st[0]) for _ in range(3)]
+        cen = (C.c_double * 6)(*[float(v) for v in centre])
+        h = make_host(host[0], host[1])
+        cs = CCadenceState(int(state["since"]), 0, int(state["nbound"]), float(state["rx"]),
+                           float(state["rhm"]), float(state["mbound"]))
+        logs = (CIntervalLog * max(int(nint), 1))()
+        cad = cadence.c()
+        ws = self.cadence_workspace(n, cadence.ns_max, device=m.device)
+        _check(lib().scf_evolve(self._h, n, *[_ptr(t) for t in st], _ptr(m),
+                                *[_ptr(t) for t in acc], C.byref(h), C.cast(cen, _dp),
+                                C.byref(cad), int(nint), _ptr(coef), _ptr(w), C.byref(cs),
+                                C.cast(logs, C.POINTER(CIntervalLog)), _ptr(ws), ws.numel(),
+                                _stream()))
+        log = [{"dt_int": e.dt_int, "nsub": e.nsub, "nsamples": e.nsamples,
+                "kind": "complete" if e.complete else "intermediate", "nbound": e.nbound,
+                "nchanged": e.nchanged, "rx": e.rx, "rhm": e.rhm, "mbound": e.mbound}
+               for e in logs[:int(nint)]]
+        return np.array(cen[:]), _state_dict(cs), log
