@@ -250,6 +250,86 @@ def run_long(torch, scf, I):
     return out
 
 
+def run_cadence(torch, scf, I, nint=10):
+    """Refresh cadence (Sec. 2.2) on the log-host workload (Plummer N = 1e5
+    at R = 20, nmax 10, lmax 6, FP32): integration intervals from the tidal
+    timestep (eta = 1/400) covered by substeps of at most the workload's dt,
+    complete refresh every 5 intervals, r <= r_99.9 selection, one orbit
+    sample per t_dyn.  Reports the whole-run time, the per-kind kernel time
+    (from a second, event-bracketed run), the plain step over the same
+    simulated time for comparison, and the selection at N = 1e6 with its
+    algorithmic HBM bytes."""
+    w = I.config2()
+    p = w.clusters[0]
+    host = (w.host, w.G)
+    cad = scf.Cadence(eta=1.0 / 400.0, dt_max=w.dt, frac=0.999, refresh_every=5, n_samples_tdyn=1,
+                      ns_max=8)
+    plan = scf.Plan(w.nmax, w.lmax, dtype="f32")
+    st0 = [torch.as_tensor(p.state()[i], dtype=torch.float32, device="cuda").contiguous()
+           for i in range(6)]
+    m = torch.as_tensor(p.mass, dtype=torch.float32, device="cuda")
+    plan.autotune(st0[0], st0[1], st0[2], m)
+
+    def fresh():
+        st = [t.clone() for t in st0]
+        coef, wts, state = plan.cadence_init(st, m, cad.frac)
+        return st, coef, wts, state
+
+    st, coef, wts, state = fresh()
+    plan.evolve(st, m, 1, cad, host, w.centres[0], coef, wts, state)  # warm-up
+    st, coef, wts, state = fresh()
+    torch.cuda.synchronize()
+    (cen, state1, log), ms = _timed(torch, lambda: plan.evolve(st, m, nint, cad, host, w.centres[0],
+                                                                coef, wts, state))
+    st, coef, wts, state = fresh()
+    plan.profile(True)
+    plan.kernel_times()
+    plan.evolve(st, m, nint, cad, host, w.centres[0], coef, wts, state)
+    kt = plan.kernel_times()
+    plan.profile(False)
+    substeps = sum(e["nsub"] for e in log)
+    t_sim = sum(e["dt_int"] for e in log)
+    # the plain step (coefficients every step) over the same simulated time
+    stp = [t.clone() for t in st0]
+    nplain = int(round(t_sim / w.dt))
+    plan.step([t.clone() for t in st0], m, w.dt, 2, host=host, centre=w.centres[0])
+    _, ms_plain = _timed(torch, lambda: plan.step(stp, m, w.dt, nplain, host=host,
+                                                   centre=w.centres[0]))
+    # the selection alone at N = 1e6 (HBM-bound kernels)
+    big = I.plummer(1_000_000, 9001)
+    sb = [torch.as_tensor(big.state()[i], dtype=torch.float32, device="cuda").contiguous()
+          for i in range(6)]
+    mb = torch.as_tensor(big.mass, dtype=torch.float32, device="cuda")
+    cb = plan.coeffs(sb[0], sb[1], sb[2], mb)
+    plan.select(sb, mb, cb, 0.999)
+    plan.profile(True)
+    plan.kernel_times()
+    for _ in range(5):
+        plan.select(sb, mb, cb, 0.999)
+    ks = plan.kernel_times()
+    plan.profile(False)
+    sel_ms = ks["select"][1] / 5 if "select" in ks else None
+    # energy + keys: x, y, z, v (6 x 4 B) + psi (4 B) in, key (4 B) + flag (1 B)
+    # out; four 8-bit digit passes over the keys (4 x 4 B); weights: key, m in,
+    # w out (12 B)
+    sel_bytes = 1_000_000 * (28 + 5 + 16 + 12)
+    return {
+        "workload": f"{w.name} (N = {p.n}), cadence eta = 1/400, dt_max = {w.dt}, "
+                    "complete refresh every 5, r <= r_99.9, 1 sample per t_dyn",
+        "intervals": nint, "substeps": substeps, "t_simulated": t_sim,
+        "ms_total": ms, "ms_per_interval": ms / nint, "us_per_substep": ms * 1e3 / substeps,
+        "plain_step_us": ms_plain * 1e3 / nplain, "plain_steps_same_time": nplain,
+        "speedup_vs_plain_same_time": ms_plain / ms,
+        "kernel_ms_total": {k: v[1] for k, v in kt.items()},
+        "intervals_log": [{k: e[k] for k in ("dt_int", "nsub", "nsamples", "kind", "nbound",
+                                             "nchanged", "rx", "rhm")} for e in log],
+        "select_N1e6": {"ms": sel_ms, "algorithmic_bytes": sel_bytes,
+                        "GB_per_s": sel_bytes / (sel_ms * 1e-3) / 1e9 if sel_ms else None,
+                        "note": "energy/key, 4 radix-digit passes and weights kernels; "
+                                "the potential evaluation before them is not included"},
+    }
+
+
 def run_adjoint(torch, scf, I, nsteps=None):
     """Plummer N = 1e5 in an NFW host, 2000 steps with checkpoints every 100:
     forward and backward times of the checkpointed autograd trajectory."""
@@ -374,6 +454,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--legs", default="all",
+                    help="comma list of extra legs (f64, accuracy, batched, adjoint, long, "
+                         "diagnostics, cadence) or 'all'")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline FP32 workload only (no FP64, batched, adjoint, accuracy)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -449,8 +532,12 @@ def main():
         "step_frac": step_tf / PEAK_FP32_TFLOPS,
     }
     del r["plan"]
+    legs = set(("f64", "accuracy", "batched", "adjoint", "long", "diagnostics", "cadence")
+               if args.legs == "all" else args.legs.split(","))
+    if args.no_f64:
+        legs.discard("f64")
     if not args.no_extras:
-        if not args.no_f64:
+        if "f64" in legs:
             print("[bench] FP64", file=sys.stderr, flush=True)
             steps64 = max(1, args.steps // 4)
             r64 = run_main("f64", steps64, max(1, args.warmup // 4), torch, scf, I, profile=False)
@@ -460,16 +547,16 @@ def main():
                           "step_tflops": tf64, "frac_fp64_peak": tf64 / PEAK_FP64_TFLOPS,
                           "f32_over_f64_speed": (r64["ms"] / steps64) / ms_per_step}
             del r64["plan"]
-        print("[bench] accuracy", file=sys.stderr, flush=True)
-        out["accuracy"] = accuracy_main(torch, scf, I)
-        print("[bench] batched", file=sys.stderr, flush=True)
-        out["batched"] = run_batched(torch, scf, I, steps=50)
-        print("[bench] adjoint", file=sys.stderr, flush=True)
-        out["adjoint"] = run_adjoint(torch, scf, I)
-        print("[bench] long runs", file=sys.stderr, flush=True)
-        out["long_runs"] = run_long(torch, scf, I)
-        print("[bench] diagnostics", file=sys.stderr, flush=True)
-        out["diagnostics"] = run_diagnostics(torch, scf, I)
+        legs_fn = [("accuracy", "accuracy", lambda: accuracy_main(torch, scf, I)),
+                   ("batched", "batched", lambda: run_batched(torch, scf, I, steps=50)),
+                   ("adjoint", "adjoint", lambda: run_adjoint(torch, scf, I)),
+                   ("long", "long runs", lambda: run_long(torch, scf, I)),
+                   ("diagnostics", "diagnostics", lambda: run_diagnostics(torch, scf, I)),
+                   ("cadence", "cadence", lambda: run_cadence(torch, scf, I))]
+        for key, label, fn in legs_fn:
+            if key in legs:
+                print(f"[bench] {label}", file=sys.stderr, flush=True)
+                out["long_runs" if key == "long" else key] = fn()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -189,3 +189,42 @@ def test_adjoint_workload_full_n_short_horizon(torch, S, O):
         assert abs(lc[q] - lc_ref[q]) <= 1e-3 * max(abs(lc_ref[q]), 1e-3 * scale), (q, lc, lc_ref)
     for k in range(2):
         assert abs(gh[0, k] - gh_ref[0, k]) <= 1e-3 * abs(gh_ref[0, k]), (k, gh, gh_ref)
+
+
+def test_cadence_workload_full_size(torch, S, O):
+    """Plummer N = 1e5 at R = 20 in the logarithmic host through the refresh
+    cadence in FP64: two integration intervals (an intermediate refresh, then
+    a complete one) against the oracle's driver."""
+    from oracle import cadence as K
+    w = I.config2()
+    p = w.clusters[0]
+    print(f"[full size] {w.name} cadence", flush=True)
+    st0 = np.asarray(p.state(), dtype=np.float64)
+    m = np.asarray(p.mass, dtype=np.float64)
+    B = O.basis(w.nmax, w.lmax)
+    H = _ohost(O, w.host)
+    eta, dt_max = 1.0 / 400.0, 0.1
+    c0, w0, i0 = K.initial_refresh(B, st0, m, 0.999)
+    st_ref, cen_ref, coef_ref, w_ref, cs_ref, log_ref = K.evolve(
+        B, H, st0, m, w.centres[0], c0, w0, 2, eta=eta, dt_max=dt_max, refresh_every=2,
+        mbound=i0["mbound"], rhm=i0["rhm"])
+    for e in log_ref:
+        assert e["emargin"] > 1e-10 and e["gap"] > 1e-10
+    plan = S.Plan(w.nmax, w.lmax, dtype="f64")
+    st = [_dev(torch, st0[i], "f64") for i in range(6)]
+    md = _dev(torch, m, "f64")
+    plan.autotune(st[0], st[1], st[2], md)
+    coef, wts, state = plan.cadence_init(st, md, 0.999)
+    cad = S.Cadence(eta=eta, dt_max=dt_max, frac=0.999, refresh_every=2, n_samples_tdyn=0)
+    cen, state, log = plan.evolve(st, md, 2, cad, (w.host, w.G), w.centres[0], coef, wts, state)
+    torch.cuda.synchronize()
+    for g, r in zip(log, log_ref):
+        for k in ("nsub", "kind", "nbound", "nchanged"):
+            assert g[k] == r[k], (k, g, r)
+    assert np.array_equal(wts.cpu().numpy(), w_ref)
+    out = _np(st)
+    for rows in (slice(0, 3), slice(3, 6)):
+        d = np.abs(out[rows] - st_ref[rows]).max() / np.abs(st_ref[rows]).max()
+        assert d <= TOL["f64"], d
+    assert np.abs(cen - cen_ref).max() <= 1e-12 * np.abs(cen_ref).max()
+    assert coef_err(coef.cpu().numpy(), coef_ref) <= TOL["f64"]
