@@ -101,7 +101,8 @@ typedef struct scf_plan scf_plan;
 
 /* scf_step flags */
 #define SCF_STEP_ACC_VALID 1u /* ax, ay, az already hold a(x) at entry */
-#define SCF_STEP_NO_GRAPH 2u  /* scf_step_batched: launch the kernels directly, no HIP graph */
+#define SCF_STEP_NO_GRAPH 2u  /* scf_step_batched: launch the kernels directly (the default) */
+#define SCF_STEP_GRAPH 4u     /* scf_step_batched: replay the middle steps from HIP graphs */
 
 /* (nmax+1)(lmax+1)^2, or 0 for negative arguments. */
 int64_t scf_ncoef(int32_t nmax, int32_t lmax);
@@ -154,11 +155,13 @@ scf_status scf_step(scf_plan* plan, int64_t n, void* x, void* y, void* z, void* 
  * One step is one launch each of the coefficient, reduction, finalisation and
  * field kernels for all clusters together, driven by static work lists (a
  * cluster's particle ranges per wave-unit, its partial rows, its 256-particle
- * field blocks) built on the host per call.  The middle steps (all but the
- * last) are captured once into a HIP graph (on a plan-owned stream; recaptured
- * when pointers, sizes, dt or the host change) and replayed on stream; with
- * SCF_STEP_NO_GRAPH the same kernels are launched directly, with bitwise
- * identical results.  The per-step centre rows are uploaded in chunks of 256
+ * field blocks) built on the host per call.  The kernels are launched
+ * directly on stream by default.  With SCF_STEP_GRAPH (and without
+ * SCF_STEP_NO_GRAPH) the middle steps (all but the last) are instead
+ * replayed from HIP graphs of one and of eight steps, captured once on a
+ * plan-owned stream and recaptured when pointers, sizes, dt or the host
+ * change; the results are bitwise identical.  On the MI355X the direct
+ * launches are the faster of the two.  The per-step centre rows are uploaded in chunks of 256
  * steps and selected on the device.  The workspace must come from
  * scf_workspace_size(plan, n, nclusters).  step_flags and the returned state
  * are as for scf_step; coef_last (device, nullable) receives nclusters*ncoef

@@ -200,6 +200,8 @@ struct scf_plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph_g = nullptr;    // kGraphSteps middle steps in one graph
+  hipGraphExec_t gexec_g = nullptr;
   std::vector<char> gkey;
   int graph_captures = 0;
   double* h_tab = nullptr;
@@ -300,6 +302,7 @@ size_t plain_need(const scf_plan* p, int64_t n) { return ws_layout(p, n, 1, 0).t
 // Batched workspace: the common layout for nclusters, then the centre-table
 // chunk, the current centre rows and step counter, and the work lists.
 constexpr int kCentreRows = 256;  // centre-table rows uploaded per chunk
+constexpr int kGraphSteps = 8;    // middle steps replayed per graph launch
 
 struct BatchLayout {
   WsLayout L;
@@ -924,6 +927,8 @@ void scf_plan_destroy(scf_plan* p) {
   }
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->gexec_g) (void)hipGraphExecDestroy(p->gexec_g);
+  if (p->graph_g) (void)hipGraphDestroy(p->graph_g);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->h_tab) (void)hipHostFree(p->h_tab);
   if (p->h_meta) (void)hipHostFree(p->h_meta);
@@ -1103,7 +1108,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
   if (nclusters < 1 || nsteps < 0) return fail(SCF_ERR_INVALID_ARG, "need nclusters >= 1 and nsteps >= 0");
   if (!offsets || !centres) return fail(SCF_ERR_INVALID_ARG, "offsets and centres must be non-null");
   if (!std::isfinite(dt)) return fail(SCF_ERR_INVALID_ARG, "dt is not finite");
-  if (step_flags & ~(SCF_STEP_ACC_VALID | SCF_STEP_NO_GRAPH))
+  if (step_flags & ~(SCF_STEP_ACC_VALID | SCF_STEP_NO_GRAPH | SCF_STEP_GRAPH))
     return fail(SCF_ERR_INVALID_ARG, "unknown step flags");
   if (offsets[0] != 0) return fail(SCF_ERR_INVALID_ARG, "offsets[0] must be 0");
   for (int c = 0; c < nclusters; ++c)
@@ -1126,7 +1131,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
   HostParams<double> hd;
   fill_host_params(hd, with_host ? host : nullptr);
   const bool acc_valid = (step_flags & SCF_STEP_ACC_VALID) && nsteps > 0;
-  const bool use_graph = !(step_flags & SCF_STEP_NO_GRAPH);
+  const bool use_graph = (step_flags & SCF_STEP_GRAPH) && !(step_flags & SCF_STEP_NO_GRAPH);
 
   // ---- work lists (host), staged in pinned memory --------------------------
   const int v = p->coef_variant;
@@ -1358,32 +1363,61 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
       if (!p->gexec || key != p->gkey) {
         if (p->gexec) HIP_TRY(hipGraphExecDestroy(p->gexec));
         if (p->graph) HIP_TRY(hipGraphDestroy(p->graph));
+        if (p->gexec_g) HIP_TRY(hipGraphExecDestroy(p->gexec_g));
+        if (p->graph_g) HIP_TRY(hipGraphDestroy(p->graph_g));
         p->gexec = nullptr;
         p->graph = nullptr;
+        p->gexec_g = nullptr;
+        p->graph_g = nullptr;
         p->gkey.clear();
         if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
-        scf_status cs = enqueue(p->cap_stream, dt, dt, coef_int);
-        hipGraph_t g = nullptr;
-        hipError_t ee = hipStreamEndCapture(p->cap_stream, &g);
-        if (cs != SCF_OK) {
-          if (g) (void)hipGraphDestroy(g);
-          return cs;
+        // one middle step, and kGraphSteps of them in a row (the centre rows
+        // advance on the device, so consecutive steps are the same nodes)
+        for (int rep : {1, kGraphSteps}) {
+          HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+          scf_status cs = SCF_OK;
+          for (int r = 0; r < rep && cs == SCF_OK; ++r) cs = enqueue(p->cap_stream, dt, dt, coef_int);
+          hipGraph_t g = nullptr;
+          hipError_t ee = hipStreamEndCapture(p->cap_stream, &g);
+          if (cs != SCF_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cs;
+          }
+          HIP_TRY(ee);
+          hipGraphExec_t ge = nullptr;
+          hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+          if (ie != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            HIP_TRY(ie);
+          }
+          if (rep == 1) {
+            p->graph = g;
+            p->gexec = ge;
+          } else {
+            p->graph_g = g;
+            p->gexec_g = ge;
+          }
         }
-        HIP_TRY(ee);
-        p->graph = g;
-        HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
         p->gkey = key;
         p->graph_captures += 1;
       }
     }
-    for (int64_t k = 1; k <= nsteps; ++k) {
+    for (int64_t k = 1; k <= nsteps;) {
       if (k - chunk0 >= kCentreRows) {
         chunk0 = k;
         st = upload_rows(k);
         if (st != SCF_OK) return st;
       }
       const bool last = k == nsteps;
+      // a run of kGraphSteps middle steps inside the current centre chunk
+      const bool group = use_graph && k + kGraphSteps - 1 < nsteps &&
+                         k + kGraphSteps - 1 - chunk0 < kCentreRows;
+      if (group) {
+        Timed t(p, s, K_BATCH_FIELD);
+        HIP_TRY(hipGraphLaunch(p->gexec_g, s));
+        k += kGraphSteps;
+        continue;
+      }
       if (!last && use_graph) {
         Timed t(p, s, K_BATCH_FIELD);
         HIP_TRY(hipGraphLaunch(p->gexec, s));
@@ -1391,6 +1425,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
         st = enqueue(s, last ? h : dt, last ? 0.0 : dt, last && coef_last ? coef_last : coef_int);
         if (st != SCF_OK) return st;
       }
+      ++k;
     }
     return SCF_OK;
   };

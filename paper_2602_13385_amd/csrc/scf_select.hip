@@ -118,18 +118,19 @@ __global__ void __launch_bounds__(256) radix_pick_kernel(SelectState* st, int sh
     __syncthreads();
   }
   for (int t = 0; t < 2; ++t) {
-    cnt[tid] = st->hist[t][tid];
+    const uint32_t c = st->hist[t][tid];
+    cnt[tid] = c;
+    scan[tid] = c;
     __syncthreads();
-    if (tid == 0) {
-      int64_t c = 0;
-      for (int b = 0; b < 256; ++b) {
-        scan[b] = c;
-        c += cnt[b];
-      }
+    // inclusive prefix sum over the 256 bins (Hillis-Steele)
+    for (int off = 1; off < 256; off <<= 1) {
+      const int64_t v = tid >= off ? scan[tid - off] : 0;
+      __syncthreads();
+      scan[tid] += v;
+      __syncthreads();
     }
-    __syncthreads();
     const int64_t r = st->rank[t];
-    const int64_t lo = scan[tid], hi = lo + cnt[tid];
+    const int64_t lo = scan[tid] - (int64_t)cnt[tid], hi = scan[tid];
     __syncthreads();
     if (st->nb > 0 && cnt[tid] > 0 && r >= lo && r < hi) {
       st->prefix[t] |= (uint64_t)tid << shift;

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libscf.so")
 F32, F64 = 0, 1
 STEP_ACC_VALID = 1
 STEP_NO_GRAPH = 2
+STEP_GRAPH = 4
 HOST_KINDS = {"log": 1, "hernquist": 2, "nfw": 3, "mn": 4, "plummer": 5}
 MAX_HOST_COMP = 8
 
@@ -407,9 +408,11 @@ class Plan:
         return int(lib().scf_plan_graph_captures(self._h))
 
     def step_batched(self, offsets, st, m, dt, nsteps, host=None, centres=None, acc=None,
-                     coef_last=None, graph=True):
+                     coef_last=None, graph=False):
         """Advance nclusters clusters concatenated in st = [x, y, z, vx, vy, vz]
         (cluster c owns [offsets[c], offsets[c+1])) in place.  centres: (nclusters, 6).
+        graph=True replays the middle steps from HIP graphs (bitwise the same
+        results; direct launches are faster on the MI355X).
         Returns (centres (nclusters, 6) numpy, acc)."""
         torch = _torch()
         self._check_arrays(*st, m)
@@ -425,7 +428,7 @@ class Plan:
         cen = np.ascontiguousarray(cen.reshape(ncl, 6))
         h = make_host(host[0], host[1]) if host is not None else None
         ws = self.workspace(n, nclusters=ncl, device=st[0].device)
-        flags = (STEP_ACC_VALID if acc_valid else 0) | (0 if graph else STEP_NO_GRAPH)
+        flags = (STEP_ACC_VALID if acc_valid else 0) | (STEP_GRAPH if graph else 0)
         _check(lib().scf_step_batched(self._h, ncl, off.ctypes.data_as(C.POINTER(C.c_int64)),
                                       *[_ptr(t) for t in st], _ptr(m), *[_ptr(t) for t in acc],
                                       flags, C.byref(h) if h is not None else None,

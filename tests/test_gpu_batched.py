@@ -70,7 +70,7 @@ def _ohost(O):
     return O.host([(kinds[k], p) for k, p in HOST])
 
 
-def _run(torch, S, plan, off, st0, m, cens, dtype, dt, nsteps, graph=True, coef=None):
+def _run(torch, S, plan, off, st0, m, cens, dtype, dt, nsteps, graph=False, coef=None):
     st = [_dev(torch, st0[i], dtype) for i in range(6)]
     md = _dev(torch, m, dtype)
     cen, acc = plan.step_batched(off, st, md, dt, nsteps, host=(HOST, 1.0), centres=cens,
@@ -125,7 +125,8 @@ def test_batched_graph_replays_equal_eager(torch, S):
     cg, ce = cens.copy(), cens.copy()
     ag = ae = None
     for call in range(3):
-        cg, ag = plan.step_batched(off, sg, md, 0.005, 4, host=(HOST, 1.0), centres=cg, acc=ag)
+        cg, ag = plan.step_batched(off, sg, md, 0.005, 4, host=(HOST, 1.0), centres=cg, acc=ag,
+                                   graph=True)
         junk = torch.randn(1 << 20, device="cuda")
         junk = (junk * 2.0).sum()
         torch.cuda.synchronize()
@@ -135,6 +136,27 @@ def test_batched_graph_replays_equal_eager(torch, S):
         for a, b in zip(sg + ag, se + ae):
             assert torch.equal(a, b), f"call {call}"
         assert np.array_equal(cg, ce)
+    assert plan.graph_captures == 1
+
+
+def test_batched_eight_step_graphs_across_centre_chunks(torch, S):
+    """300 steps: runs of middle steps replay the eight-step graph, the others
+    the one-step graph, and the centre table is re-uploaded after 256 steps;
+    the result equals the directly launched kernels bitwise."""
+    sizes = [3000, 1200]
+    off, st0, m, cens = _clusters(sizes, 4403)
+    plan = S.Plan(6, 4, dtype="f32")
+    md = _dev(torch, m, "f32")
+    sg = [_dev(torch, st0[i], "f32") for i in range(6)]
+    se = [_dev(torch, st0[i], "f32") for i in range(6)]
+    cg, ag = plan.step_batched(off, sg, md, 0.004, 300, host=(HOST, 1.0), centres=cens,
+                               graph=True)
+    ce, ae = plan.step_batched(off, se, md, 0.004, 300, host=(HOST, 1.0), centres=cens,
+                               graph=False)
+    torch.cuda.synchronize()
+    for a, b in zip(sg + ag, se + ae):
+        assert torch.equal(a, b)
+    assert np.array_equal(cg, ce)
     assert plan.graph_captures == 1
 
 
