@@ -312,6 +312,27 @@ scf_status scf_evolve(scf_plan* plan, int64_t n, void* x, void* y, void* z, void
                       int32_t nint, double* coef, void* w, scf_cadence_state* state,
                       scf_interval_log* log, void* ws, size_t ws_bytes, void* stream);
 
+/* Density and frame core (Sec. 2, Eq. total_dens; Sec. 2.1).
+ * scf_density: rho_SCF = sum a_nlm D_n^l Y_l^m at n points (rho: device, n,
+ * plan dtype) from coef (device).  The density basis follows from Poisson's
+ * equation, nabla^2 psi^(nlm) = 4 pi G rho^(nlm), in closed form through the
+ * Gegenbauer differential equation:
+ *     D_n^l(r) = -K_nl s^(1/alpha - 2) (1 + s^(1/alpha))^(-2) U_n^l(r) / (4 pi G b^2),
+ *     K_nl = [n(n + 2 lambda_l) + p_l(p_l + 1)] / alpha^2,  p_l = alpha(2l+1).
+ * At r = 0 the value is not finite for alpha > 1/2 (the basis' central cusp).
+ * scf_core: over the particles with w > 0 (device, plan dtype), the core
+ * radius r_core = sqrt(sum rho^2 r^2 / sum rho^2) with rho = rho_SCF of coef at
+ * each particle, and the mass-weighted mean velocity of those with r <= r_core
+ * (the frame velocity of Sec. 2.1); r^2 is formed in double precision.
+ * out (host, 5 doubles) = r_core, v_core[3], core mass; all zero when no
+ * particle has w > 0.  Blocks.  Both use the workspace of
+ * scf_cadence_workspace_size(plan, n, 1). */
+scf_status scf_density(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
+                       const double* coef, void* rho, void* ws, size_t ws_bytes, void* stream);
+scf_status scf_core(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
+                    const void* vx, const void* vy, const void* vz, const void* m, const void* w,
+                    const double* coef, double* out, void* ws, size_t ws_bytes, void* stream);
+
 /* Launch configuration.  The coefficient kernel has several compiled
  * variants (lanes per particle in the basis phase, waves per block).
  * scf_autotune times each on the given particles (synchronising the stream)

@@ -185,6 +185,50 @@ def field(B, coef, x, y, z, pot=True, acc=True):
     return P, (np.stack([gx, gy, gz]) if acc else None)
 
 
+def density_scale(B):
+    """K_nl = [n(n + 2 lambda_l) + p_l (p_l + 1)] / alpha^2, p_l = alpha (2l+1),
+    lambda_l = p_l + 1/2, per stored coefficient: the radial Laplacian of
+    s^l (1 + s^(1/alpha))^(-p) C_n^lambda(xi) is -K_nl s^(1/alpha - 2)
+    (1 + s^(1/alpha))^(-2) times that same function (from the Gegenbauer
+    differential equation)."""
+    L2 = (B.lmax + 1) ** 2
+    K = np.zeros(ncoef(B.nmax, B.lmax))
+    for n in range(B.nmax + 1):
+        for l in range(B.lmax + 1):
+            p = B.alpha * (2 * l + 1)
+            lam = p + 0.5
+            K[n * L2 + l * l: n * L2 + (l + 1) ** 2] = (n * (n + 2 * lam) + p * (p + 1)) / B.alpha ** 2
+    return K
+
+
+def density(B, coef, x, y, z):
+    """rho_SCF = sum a_nlm D_n^l Y_l^m (Eq. total_dens), with the density basis
+    D = nabla^2 U / (4 pi G): rho = -s^(1/alpha-2) (1 + s^(1/alpha))^(-2)
+    / (4 pi G b^2) times the potential of the coefficients K_nl a_nlm."""
+    x, y, z = map(_f64, (x, y, z))
+    pot, _ = field(B, np.asarray(coef, dtype=np.float64) * density_scale(B), x, y, z, acc=False)
+    s = np.sqrt(x * x + y * y + z * z) / B.b
+    t = s ** (1.0 / B.alpha)
+    return -(s ** (1.0 / B.alpha - 2.0)) / (1.0 + t) ** 2 / (4.0 * np.pi * B.G * B.b ** 2) * pot
+
+
+def core(B, coef, state, m, w):
+    """Frame velocity of Sec. 2.1 over the particles with w > 0:
+    r_core = sqrt(sum rho^2 r^2 / sum rho^2) with rho = rho_SCF at each, and
+    the mass-weighted mean velocity of those with r <= r_core.
+    Returns (r_core, v_core (3,), core mass)."""
+    st = np.asarray(state, dtype=np.float64)
+    sel = np.asarray(w) > 0
+    rho = density(B, coef, st[0], st[1], st[2])
+    r2 = (st[:3] ** 2).sum(0)
+    q = rho[sel] ** 2
+    rc2 = (q * r2[sel]).sum() / q.sum()
+    inc = sel & (r2 <= rc2)
+    mm = np.asarray(m, dtype=np.float64)[inc]
+    v = (st[3:, inc] * mm).sum(1) / mm.sum()
+    return float(np.sqrt(rc2)), v, float(mm.sum())
+
+
 def host_eval(H, pos):
     pos = _f64(pos)
     pot = np.zeros(1)

@@ -185,6 +185,7 @@ struct scf_plan {
   void* d_beta_ang = nullptr;
   double* d_cs = nullptr;
   double* d_fw = nullptr;
+  double* d_kden = nullptr;  // density constants -K_nl / (4 pi G b^2), [l][n]
   std::vector<double> h_cs, h_fw;
   // kernel timing
   bool prof = false;
@@ -910,6 +911,21 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
   if (e == hipSuccess) e = hipMemcpy(p->d_cs, p->h_cs.data(), p->T * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&p->d_fw, p->T * 8);
   if (e == hipSuccess) e = hipMemcpy(p->d_fw, p->h_fw.data(), p->T * 8, hipMemcpyHostToDevice);
+  {
+    // density basis: the radial Laplacian of s^l (1 + s^(1/alpha))^(-p) C_n^lambda(xi)
+    // is -K_nl s^(1/alpha - 2) (1 + s^(1/alpha))^(-2) times the same function,
+    // K_nl = [n(n + 2 lambda) + p(p + 1)] / alpha^2, p = alpha (2l + 1)
+    std::vector<double> kd((size_t)L1 * NW, 0.0);
+    const double a = basis->alpha;
+    for (int l = 0; l <= p->lmax; ++l)
+      for (int n = 0; n <= p->nmax; ++n) {
+        const double pp = a * (2.0 * l + 1.0), lam = pp + 0.5;
+        const double K = (n * (n + 2.0 * lam) + pp * (pp + 1.0)) / (a * a);
+        kd[(size_t)l * NW + n] = -K / (4.0 * M_PI * basis->G * basis->b * basis->b);
+      }
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_kden, kd.size() * 8);
+    if (e == hipSuccess) e = hipMemcpy(p->d_kden, kd.data(), kd.size() * 8, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     scf_plan_destroy(p);
     return fail(SCF_ERR_HIP, "plan allocation failed: %s", hipGetErrorString(e));
@@ -934,6 +950,7 @@ void scf_plan_destroy(scf_plan* p) {
   if (p->h_meta) (void)hipHostFree(p->h_meta);
   if (p->d_beta_rad) (void)hipFree(p->d_beta_rad);
   if (p->d_beta_ang) (void)hipFree(p->d_beta_ang);
+  if (p->d_kden) (void)hipFree(p->d_kden);
   if (p->d_cs) (void)hipFree(p->d_cs);
   if (p->d_fw) (void)hipFree(p->d_fw);
   delete p;
@@ -1637,7 +1654,8 @@ namespace {
 // samples and two coefficient vectors.
 struct CadLayout {
   WsLayout L;
-  size_t pot, keys, bound, state, mpart, cnt, off, total, acc, wnew, compact, snaps, ctmp, all;
+  size_t pot, keys, bound, state, mpart, cnt, off, total, acc, wnew, compact, snaps, ctmp, mom,
+      res, all;
 };
 
 CadLayout cad_layout(const scf_plan* p, int64_t n, int ns_max) {
@@ -1664,6 +1682,8 @@ CadLayout cad_layout(const scf_plan* p, int64_t n, int ns_max) {
   C.compact = take((3 * (size_t)ns_max + 1) * nn * rs);
   C.snaps = take(3 * (size_t)ns_max * nn * rs);
   C.ctmp = take((size_t)p->T * 8);
+  C.mom = take(nblk * 4 * 8);
+  C.res = take(4 * 8);
   C.all = off;
   return C;
 }
@@ -2135,6 +2155,92 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
     centre[3 + i] = V[i];
   }
   return st;
+}
+
+
+}  // extern "C"
+
+namespace {
+
+// rho_SCF (Eq. total_dens) of coef at n points into rho: the field pass's psi
+// with density-scaled weights, times the radial factor
+template <typename R>
+scf_status density_impl(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                        const double* coef, void* rho, char* ws, const CadLayout& C, hipStream_t s) {
+  void* W = ws + C.L.W;
+  {
+    Timed t(p, s, K_MAKE_W);
+    HIP_TRY(launch_make_w(p->dtype, coef, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_fw, W, s));
+    HIP_TRY(launch_scale_w(p->dtype, W, p->d_kden, p->lmax, p->nmaxc, s));
+  }
+  HostParams<R> none;
+  std::memset(&none, 0, sizeof(none));
+  const size_t nr = (size_t)n * p->rs;
+  char* acc = ws + C.acc;
+  scf_status st = run_field<R>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, acc,
+                               acc + nr, acc + 2 * nr, rho, W, none, nullptr, 0, 0.0, 0.0, s);
+  if (st != SCF_OK) return st;
+  Timed t(p, s, K_SELECT);
+  HIP_TRY(launch_density_factor(p->dtype, n, x, y, z, 1.0 / p->basis.b, 1.0 / p->basis.alpha,
+                                p->amode, rho, s));
+  return SCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+scf_status scf_density(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                       const double* coef, void* rho, void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !coef) return fail(SCF_ERR_INVALID_ARG, "plan and coef must be non-null");
+  if (n < 0) return fail(SCF_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+  if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(rho)))
+    return fail(SCF_ERR_INVALID_ARG, "point and output arrays must be non-null");
+  scf_status cs = check_cadence_ws(p, n, 1, ws, ws_bytes);
+  if (cs != SCF_OK) return cs;
+  const CadLayout C = cad_layout(p, n, 1);
+  hipStream_t s = (hipStream_t)stream;
+  return p->dtype == SCF_F32 ? density_impl<float>(p, n, x, y, z, coef, rho, (char*)ws, C, s)
+                             : density_impl<double>(p, n, x, y, z, coef, rho, (char*)ws, C, s);
+}
+
+scf_status scf_core(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                    const void* vx, const void* vy, const void* vz, const void* m, const void* w,
+                    const double* coef, double* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !coef || !out) return fail(SCF_ERR_INVALID_ARG, "plan, coef and out must be non-null");
+  if (n < 0) return fail(SCF_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+  if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(vx) && ptr_ok(vy) && ptr_ok(vz) &&
+                 ptr_ok(m) && ptr_ok(w)))
+    return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
+  scf_status cs = check_cadence_ws(p, n, 1, ws, ws_bytes);
+  if (cs != SCF_OK) return cs;
+  const CadLayout C = cad_layout(p, n, 1);
+  hipStream_t s = (hipStream_t)stream;
+  char* wsp = (char*)ws;
+  void* rho = wsp + C.pot;
+  scf_status st = p->dtype == SCF_F32 ? density_impl<float>(p, n, x, y, z, coef, rho, wsp, C, s)
+                                      : density_impl<double>(p, n, x, y, z, coef, rho, wsp, C, s);
+  if (st != SCF_OK) return st;
+  double r[4];
+  {
+    Timed t(p, s, K_SELECT);
+    HIP_TRY(launch_core_moments(p->dtype, n, x, y, z, vx, vy, vz, m, w, rho, 0, 0.0,
+                                (double*)(wsp + C.mom), (double*)(wsp + C.res), s));
+  }
+  HIP_TRY(hipMemcpyAsync(r, wsp + C.res, sizeof(r), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double rc2 = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+  {
+    Timed t(p, s, K_SELECT);
+    HIP_TRY(launch_core_moments(p->dtype, n, x, y, z, vx, vy, vz, m, w, rho, 1, rc2,
+                                (double*)(wsp + C.mom), (double*)(wsp + C.res), s));
+  }
+  HIP_TRY(hipMemcpyAsync(r, wsp + C.res, sizeof(r), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out[0] = std::sqrt(rc2);
+  for (int k = 0; k < 3; ++k) out[1 + k] = r[3] > 0.0 ? r[k] / r[3] : 0.0;
+  out[4] = r[3];
+  return SCF_OK;
 }
 
 }  // extern "C"

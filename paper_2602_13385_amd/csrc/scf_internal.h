@@ -208,5 +208,18 @@ hipError_t launch_delta_compact(int dtype, int64_t n, const void* w0, const void
                                 int64_t* total, void* out, int64_t cap, hipStream_t s);
 // y += a x on n doubles
 hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);
+// density (Eq. total_dens): force weights scaled by kd[l][n], then the radial
+// factor s^(1/alpha-2) (1 + s^(1/alpha))^-2 applied to the field pass's psi
+hipError_t launch_scale_w(int dtype, void* W, const double* kd, int lmax, int nmaxc,
+                          hipStream_t s);
+hipError_t launch_density_factor(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                                 double binv, double inv_alpha, int amode, void* rho,
+                                 hipStream_t s);
+// core moments over w > 0 (mode 0: rho^2 r^2, rho^2; mode 1, r^2 <= r2max:
+// m v, m): block sums into part[nblk][4], their fixed-order sum into res[4]
+hipError_t launch_core_moments(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                               const void* vx, const void* vy, const void* vz, const void* m,
+                               const void* w, const void* rho, int mode, double r2max,
+                               double* part, double* res, hipStream_t s);
 
 }  // namespace scf

@@ -267,6 +267,105 @@ __global__ void __launch_bounds__(256) axpy_kernel(int64_t n, double a, const do
   if (i < n) y[i] += a * x[i];
 }
 
+// ---- density (Eq. total_dens) and the core of Sec. 2.1 ---------------------
+// W rows of degree l scaled by kd[l][n] (the density constants times
+// -1/(4 pi G b^2)); layout W[(l^2 + j) NW + n]
+template <typename R>
+__global__ void __launch_bounds__(256) scale_w_kernel(R* __restrict__ W, const double* __restrict__ kd,
+                                                      int lmax, int nw) {
+  const int L2 = (lmax + 1) * (lmax + 1);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= L2 * nw) return;
+  const int n = i % nw, lj = i / nw;
+  int l = 0;
+  while ((l + 1) * (l + 1) <= lj) ++l;
+  W[i] = R((double)W[i] * kd[l * nw + n]);
+}
+
+// rho = s^(1/alpha - 2) (1 + s^(1/alpha))^(-2) psi_K, s = r/b (in place)
+template <typename R>
+__global__ void __launch_bounds__(256) density_factor_kernel(int64_t n, const R* __restrict__ x,
+                                                             const R* __restrict__ y,
+                                                             const R* __restrict__ z, R binv,
+                                                             R inv_alpha, int amode,
+                                                             R* __restrict__ rho) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const R s = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]) * binv;
+  R f;
+  if (amode == 0) {
+    f = R(1) / (s * (R(1) + s) * (R(1) + s));
+  } else if (amode == 1) {
+    const R t = s * s;
+    f = R(1) / ((R(1) + t) * (R(1) + t));
+  } else {
+    const R t = pow(s, inv_alpha);
+    f = pow(s, inv_alpha - R(2)) / ((R(1) + t) * (R(1) + t));
+  }
+  rho[i] *= f;
+}
+
+// Block sums (fixed order) over the particles with w > 0 of
+//   mode 0: rho^2 r^2, rho^2
+//   mode 1 (r^2 <= r2max only): m vx, m vy, m vz, m
+// with r^2 = (x x + y y) + z z in double precision; out[blk][4].
+template <typename R>
+__global__ void __launch_bounds__(256) core_moments_kernel(int64_t n, const R* __restrict__ x,
+                                                           const R* __restrict__ y,
+                                                           const R* __restrict__ z,
+                                                           const R* __restrict__ vx,
+                                                           const R* __restrict__ vy,
+                                                           const R* __restrict__ vz,
+                                                           const R* __restrict__ m,
+                                                           const R* __restrict__ w,
+                                                           const R* __restrict__ rho, int mode,
+                                                           double r2max, double* __restrict__ out) {
+#pragma clang fp contract(off)
+  __shared__ double red[4][256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < n && w[i] > R(0)) {
+    const double xi = x[i], yi = y[i], zi = z[i];
+    const double r2 = (xi * xi + yi * yi) + zi * zi;
+    if (mode == 0) {
+      const double d = rho[i];
+      q[1] = d * d;
+      q[0] = q[1] * r2;
+    } else if (r2 <= r2max) {
+      const double mi = m[i];
+      q[0] = mi * (double)vx[i];
+      q[1] = mi * (double)vy[i];
+      q[2] = mi * (double)vz[i];
+      q[3] = mi;
+    }
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = q[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[(int64_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// the block sums of core_moments_kernel added in a fixed order: res[4]
+__global__ void __launch_bounds__(256) moments_sum_kernel(const double* __restrict__ part,
+                                                          int64_t nblk, double* __restrict__ res) {
+  __shared__ double red[4][256];
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t b = threadIdx.x; b < nblk; b += 256)
+    for (int k = 0; k < 4; ++k) q[k] += part[b * 4 + k];
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = q[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) res[threadIdx.x] = red[threadIdx.x][0];
+}
+
 inline unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -344,6 +443,52 @@ hipError_t launch_delta_compact(int dtype, int64_t n, const void* w0, const void
 hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   axpy_kernel<<<blocks_of(n), 256, 0, s>>>(n, a, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_w(int dtype, void* W, const double* kd, int lmax, int nmaxc,
+                          hipStream_t s) {
+  const int nw = nmaxc + 1, cnt = (lmax + 1) * (lmax + 1) * nw;
+  if (dtype == 0)
+    scale_w_kernel<float><<<blocks_of(cnt), 256, 0, s>>>((float*)W, kd, lmax, nw);
+  else
+    scale_w_kernel<double><<<blocks_of(cnt), 256, 0, s>>>((double*)W, kd, lmax, nw);
+  return hipGetLastError();
+}
+
+hipError_t launch_density_factor(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                                 double binv, double inv_alpha, int amode, void* rho,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (dtype == 0)
+    density_factor_kernel<float><<<blocks_of(n), 256, 0, s>>>(
+        n, (const float*)x, (const float*)y, (const float*)z, (float)binv, (float)inv_alpha, amode,
+        (float*)rho);
+  else
+    density_factor_kernel<double><<<blocks_of(n), 256, 0, s>>>(
+        n, (const double*)x, (const double*)y, (const double*)z, binv, inv_alpha, amode,
+        (double*)rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_moments(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                               const void* vx, const void* vy, const void* vz, const void* m,
+                               const void* w, const void* rho, int mode, double r2max,
+                               double* part, double* res, hipStream_t s) {
+  const int64_t nblk = n > 0 ? (int64_t)blocks_of(n) : 0;
+  if (n > 0) {
+    if (dtype == 0)
+      core_moments_kernel<float><<<blocks_of(n), 256, 0, s>>>(
+          n, (const float*)x, (const float*)y, (const float*)z, (const float*)vx,
+          (const float*)vy, (const float*)vz, (const float*)m, (const float*)w,
+          (const float*)rho, mode, r2max, part);
+    else
+      core_moments_kernel<double><<<blocks_of(n), 256, 0, s>>>(
+          n, (const double*)x, (const double*)y, (const double*)z, (const double*)vx,
+          (const double*)vy, (const double*)vz, (const double*)m, (const double*)w,
+          (const double*)rho, mode, r2max, part);
+  }
+  moments_sum_kernel<<<1, 256, 0, s>>>(part, nblk, res);
   return hipGetLastError();
 }
 

@@ -148,6 +148,9 @@ SIGNATURES = {
                              C.POINTER(CHost), _dp, C.POINTER(CCadence), C.c_int32, _vp, _vp,
                              C.POINTER(CCadenceState), C.POINTER(CIntervalLog), _vp, C.c_size_t,
                              _vp]),
+    "scf_density": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "scf_core": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, _vp,
+                           C.c_size_t, _vp]),
     "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
     "scf_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -535,3 +538,25 @@ class Plan:
                 "nchanged": e.nchanged, "rx": e.rx, "rhm": e.rhm, "mbound": e.mbound}
                for e in logs[:int(nint)]]
         return np.array(cen[:]), _state_dict(cs), log
+
+    def density(self, x, y, z, coef):
+        """rho_SCF (Eq. total_dens) at the points (device tensor)."""
+        torch = _torch()
+        self._check_arrays(x, y, z)
+        n = x.numel()
+        rho = torch.empty_like(x)
+        ws = self.cadence_workspace(n, 1, device=x.device)
+        _check(lib().scf_density(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(coef), _ptr(rho),
+                                 _ptr(ws), ws.numel(), _stream()))
+        return rho
+
+    def core(self, st, m, w, coef):
+        """Core radius and velocity (Sec. 2.1) over the particles with w > 0:
+        returns (r_core, v_core (3,), core mass)."""
+        self._check_arrays(*st, m, w)
+        n = m.numel()
+        out = (C.c_double * 5)()
+        ws = self.cadence_workspace(n, 1, device=m.device)
+        _check(lib().scf_core(self._h, n, *[_ptr(t) for t in st], _ptr(m), _ptr(w), _ptr(coef),
+                              C.cast(out, _dp), _ptr(ws), ws.numel(), _stream()))
+        return out[0], np.array(out[1:4]), out[4]
