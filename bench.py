@@ -302,6 +302,14 @@ def run_cadence(torch, scf, I, nint=10):
     plan.profile(False)
     substeps = sum(e["nsub"] for e in log)
     t_sim = sum(e["dt_int"] for e in log)
+    # the same run with the frame moved at complete refreshes (Sec. 2.1)
+    cad_r = scf.Cadence(eta=cad.eta, dt_max=cad.dt_max, frac=cad.frac,
+                        refresh_every=cad.refresh_every, n_samples_tdyn=cad.n_samples_tdyn,
+                        ns_max=cad.ns_max, recentre=True)
+    st, coef, wts, state = fresh()
+    torch.cuda.synchronize()
+    (cen_r, _, log_r), ms_r = _timed(torch, lambda: plan.evolve(st, m, nint, cad_r, host,
+                                                                 w.centres[0], coef, wts, state))
     # the plain step (coefficients every step) over the same simulated time
     stp = [t.clone() for t in st0]
     nplain = int(round(t_sim / w.dt))
@@ -336,6 +344,10 @@ def run_cadence(torch, scf, I, nint=10):
         "kernel_ms_total": {k: v[1] for k, v in kt.items()},
         "intervals_log": [{k: e[k] for k in ("dt_int", "nsub", "nsamples", "kind", "nbound",
                                              "nchanged", "rx", "rhm")} for e in log],
+        "recentre": {"ms_total": ms_r, "ms_per_interval": ms_r / nint,
+                     "frame_shifts": [{"interval": i, "dx": [float(v) for v in e["dx"]],
+                                       "dv": [float(v) for v in e["dv"]]}
+                                      for i, e in enumerate(log_r) if e["kind"] == "complete"]},
         "select_N1e6": {"ms": sel_ms, "algorithmic_bytes": sel_bytes,
                         "GB_per_s": sel_bytes / (sel_ms * 1e-3) / 1e9 if sel_ms else None,
                         "note": "energy/key, 4 radix-digit passes and weights kernels; "
@@ -454,10 +466,22 @@ def cpu_baseline(nsample=1_000_000, reps=2):
         O.field(B, c, *pos, pot=False)
     t = time.perf_counter() - t0
     T = O.ncoef(w.nmax, w.lmax)
-    return {"value": reps * nsample * T / t, "unit": "particle-terms/s", "cores": O.num_threads(),
+    cores = O.num_threads()
+    # the same passes on one core, over a 2e4-particle slice
+    n1 = 20_000
+    O.set_threads(1)
+    t1 = time.perf_counter()
+    c1 = O.coeffs(B, *pos[:, :n1], mass[:n1])
+    O.field(B, c1, *pos[:, :n1], pot=False)
+    t1 = time.perf_counter() - t1
+    O.set_threads(cores)
+    return {"value": reps * nsample * T / t, "unit": "particle-terms/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{reps} coefficient + field passes of the FP64 oracle over the {nsample} "
-                      f"particles of the Hernquist N=1e6 nmax=16 lmax=10 workload ({t:.1f} s)"}
+                      f"particles of the Hernquist N=1e6 nmax=16 lmax=10 workload ({t:.1f} s)",
+            "single_core_value": n1 * T / t1,
+            "single_core_sample": f"one coefficient + field pass over the first {n1} of those "
+                                  f"particles on 1 thread ({t1:.1f} s)"}
 
 
 def main():

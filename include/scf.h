@@ -224,7 +224,12 @@ scf_status scf_tidal_norm(const scf_host* host, const double* pos, double* norm)
  * bound mass M_b and r_hm = r_50 of the previous selection; sample j is the
  * positions after substep ceil((j+1) nsub / N_s), and a refresh averages its
  * sums over the samples.  Radii are compared through |x|^2 = (x x + y y) + z z
- * with every operation rounded in the plan's precision. */
+ * with every operation rounded in the plan's precision.  With recentre set, a
+ * complete refresh first moves the frame origin to the maximum of a_000 over
+ * the selected particles (scf_recentre from the current origin, tol 1e-6 b,
+ * at most 100 steps; positions, samples and the centre orbit's R shift), then
+ * computes the coefficients, then moves the frame velocity to the core
+ * velocity of the new potential (scf_core; velocities and V shift). */
 #define SCF_MAX_SAMPLES 16
 typedef struct {
   double eta;             /* Eq. tidal_timestep parameter (1/400 in the paper), > 0 */
@@ -235,7 +240,8 @@ typedef struct {
   int32_t refresh_every;  /* complete refresh every this many intervals (5), >= 1 */
   int32_t n_samples_tdyn; /* orbit samples per t_dyn (the paper: 1); 0: one sample at the end */
   int32_t ns_max;         /* most samples per interval, 1..SCF_MAX_SAMPLES */
-  int32_t pad;
+  int32_t recentre;       /* 1: at complete refreshes move the frame to the a_000 maximum
+                             and the core velocity (scf_recentre, scf_core) */
 } scf_cadence;
 
 /* Cadence state carried between calls (host, in/out). */
@@ -255,6 +261,7 @@ typedef struct {
   int32_t complete, pad;  /* 1: complete refresh, 0: intermediate */
   int64_t nbound, nchanged; /* bound particles; particles whose weight changed */
   double rx, rhm, mbound;
+  double dx[3], dv[3];    /* frame shift applied at this interval's end (recentre) */
 } scf_interval_log;
 
 /* Workspace bytes for scf_select, scf_coeffs_delta, scf_cadence_init and
@@ -332,6 +339,20 @@ scf_status scf_density(scf_plan* plan, int64_t n, const void* x, const void* y, 
 scf_status scf_core(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
                     const void* vx, const void* vy, const void* vz, const void* m, const void* w,
                     const double* coef, double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Frame centre (Sec. 2.1): the origin that maximises the monopole
+ * coefficient a_000 of the particles with w > 0.  About c, a_000(c) is
+ * proportional to sum_k w_k g(|x_k - c|), g(r) = (1 + (r/b)^(1/alpha))^(-alpha)
+ * (Eq. u00); its stationary points satisfy c = sum w omega x / sum w omega
+ * with omega = -g'(r)/r, and this fixed-point iteration (which never lowers
+ * a_000) runs from centre (host in/out, 3 doubles) until a step is at most
+ * tol * b or maxit steps are taken (*steps, nullable, receives the count).
+ * Particles within 1e-9 b of the current point are left out of a step.  The
+ * per-particle terms and sums are in double precision.  Blocks; workspace of
+ * scf_cadence_workspace_size(plan, n, 1). */
+scf_status scf_recentre(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
+                        const void* w, double* centre, double tol, int32_t maxit, int32_t* steps,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /* Launch configuration.  The coefficient kernel has several compiled
  * variants (lanes per particle in the basis phase, waves per block).

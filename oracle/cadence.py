@@ -43,6 +43,7 @@ import math
 
 import numpy as np
 
+from oracle import frame as F
 from oracle import pyoracle as O
 
 # t_dyn / 4.3451 Myr = (M / 1e5 Msun)^(-1/2) (r_hm / 10 pc)^(3/2) (Sec. 2.2),
@@ -159,10 +160,13 @@ def initial_refresh(B, state, m, frac, key_dtype=np.float64):
 
 def evolve(B, H, state, m, centre, coef, w, nint, *, eta, dt_max, frac=0.999,
            refresh_every=5, n_samples_tdyn=0, c_dyn=C_DYN, ns_max=8, since=0, mbound=0.0,
-           rhm=0.0, key_dtype=np.float64):
+           rhm=0.0, key_dtype=np.float64, recentre=False):
     """nint integration intervals of the cadence.  Returns the state, centre,
     coefficients, weights, the cadence state (since, mbound, rhm) and one log
-    entry per interval."""
+    entry per interval.  With recentre, a complete refresh first moves the
+    frame origin to the a_000 maximum of the selected particles (Sec. 2.1;
+    positions, samples and the centre shift), computes the coefficients, then
+    moves the frame velocity to the core velocity of the new potential."""
     st = np.array(state, dtype=np.float64, copy=True)
     cen = np.array(centre, dtype=np.float64, copy=True)
     coef = np.array(coef, dtype=np.float64, copy=True)
@@ -183,9 +187,20 @@ def evolve(B, H, state, m, centre, coef, w, nint, *, eta, dt_max, frac=0.999,
             snaps.append(st[:3].copy())
         w_new, _, info = select(B, coef, st, m, frac, key_dtype)
         since += 1
+        dx, dv = np.zeros(3), np.zeros(3)
         if since >= refresh_every:
+            nchanged = int((w_new != w).sum())
+            if recentre:
+                dx, _ = F.recentre(B, st[:3], w_new, tol=1e-6, maxit=100)
+                st[:3] -= dx[:, None]
+                snaps = [s - dx[:, None] for s in snaps[:-1]] + [st[:3].copy()]
+                cen[:3] += dx
             coef = complete_refresh(B, snaps, w_new)
-            since, kind, nchanged = 0, "complete", int((w_new != w).sum())
+            if recentre:
+                _, dv, _ = O.core(B, coef, st, m, w_new)
+                st[3:] -= dv[:, None]
+                cen[3:] += dv
+            since, kind = 0, "complete"
         else:
             coef, nchanged = intermediate_refresh(B, coef, snaps, w, w_new)
             kind = "intermediate"
@@ -194,5 +209,5 @@ def evolve(B, H, state, m, centre, coef, w, nint, *, eta, dt_max, frac=0.999,
         log.append({"dt_int": dti, "nsub": nsub, "nsamples": ns, "kind": kind,
                     "nbound": info["nbound"], "nchanged": nchanged, "rx": info["rx"],
                     "rhm": rhm, "mbound": mbound, "emargin": info["emargin"],
-                    "gap": info["gap"], "ns_ratio": ratio})
+                    "gap": info["gap"], "ns_ratio": ratio, "dx": dx, "dv": dv})
     return st, cen, coef, w, (since, mbound, rhm), log

@@ -54,6 +54,8 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.orc_num_threads.restype = C.c_int32
         L.orc_num_threads.argtypes = []
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_ncoef.restype = C.c_int64
         L.orc_ncoef.argtypes = [C.c_int32, C.c_int32]
         L.orc_gegenbauer.restype = C.c_double
@@ -118,6 +120,10 @@ def host(components, G=1.0):
         for k in range(3):
             h.comp[i].p[k] = float(pp[k])
     return h
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
 
 
 def num_threads():

@@ -58,6 +58,14 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int32_t orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

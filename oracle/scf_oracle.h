@@ -49,8 +49,9 @@ typedef struct {
 
 int64_t orc_ncoef(int32_t nmax, int32_t lmax);
 
-/* OpenMP threads the oracle's parallel loops use. */
+/* OpenMP threads the oracle's parallel loops use, and a setter (n > 0). */
 int32_t orc_num_threads(void);
+void orc_set_threads(int32_t n);
 
 /* Gegenbauer polynomial C_n^lambda(x) by the three-term recurrence. */
 double orc_gegenbauer(int32_t n, double lambda, double x);

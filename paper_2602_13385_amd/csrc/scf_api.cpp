@@ -1878,6 +1878,89 @@ int samples_for(double dti, double mb, double rhm, const scf_cadence* c, double 
   return std::min(ns, std::min(nsub, c->ns_max));
 }
 
+// rho_SCF (Eq. total_dens) of coef at n points into rho: the field pass's psi
+// with density-scaled weights, times the radial factor
+template <typename R>
+scf_status density_impl(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                        const double* coef, void* rho, char* ws, const CadLayout& C, hipStream_t s) {
+  void* W = ws + C.L.W;
+  {
+    Timed t(p, s, K_MAKE_W);
+    HIP_TRY(launch_make_w(p->dtype, coef, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_fw, W, s));
+    HIP_TRY(launch_scale_w(p->dtype, W, p->d_kden, p->lmax, p->nmaxc, s));
+  }
+  HostParams<R> none;
+  std::memset(&none, 0, sizeof(none));
+  const size_t nr = (size_t)n * p->rs;
+  char* acc = ws + C.acc;
+  scf_status st = run_field<R>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, acc,
+                               acc + nr, acc + 2 * nr, rho, W, none, nullptr, 0, 0.0, 0.0, s);
+  if (st != SCF_OK) return st;
+  Timed t(p, s, K_SELECT);
+  HIP_TRY(launch_density_factor(p->dtype, n, x, y, z, 1.0 / p->basis.b, 1.0 / p->basis.alpha,
+                                p->amode, rho, s));
+  return SCF_OK;
+}
+
+// core radius and velocity (Sec. 2.1) over w > 0: out = r_core, v[3], mass
+template <typename R>
+scf_status core_impl(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                     const void* vx, const void* vy, const void* vz, const void* m, const void* w,
+                     const double* coef, double* out, char* ws, const CadLayout& C, hipStream_t s) {
+  void* rho = ws + C.pot;
+  scf_status st = density_impl<R>(p, n, x, y, z, coef, rho, ws, C, s);
+  if (st != SCF_OK) return st;
+  double r[4];
+  {
+    Timed t(p, s, K_SELECT);
+    HIP_TRY(launch_core_moments(p->dtype, n, x, y, z, vx, vy, vz, m, w, rho, 0, 0.0,
+                                (double*)(ws + C.mom), (double*)(ws + C.res), s));
+  }
+  HIP_TRY(hipMemcpyAsync(r, ws + C.res, sizeof(r), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double rc2 = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+  {
+    Timed t(p, s, K_SELECT);
+    HIP_TRY(launch_core_moments(p->dtype, n, x, y, z, vx, vy, vz, m, w, rho, 1, rc2,
+                                (double*)(ws + C.mom), (double*)(ws + C.res), s));
+  }
+  HIP_TRY(hipMemcpyAsync(r, ws + C.res, sizeof(r), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out[0] = std::sqrt(rc2);
+  for (int k = 0; k < 3; ++k) out[1 + k] = r[3] > 0.0 ? r[k] / r[3] : 0.0;
+  out[4] = r[3];
+  return SCF_OK;
+}
+
+// fixed-point search for the a_000 maximum from c (in/out)
+scf_status recentre_impl(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                         const void* w, double* c, double tol, int maxit, int32_t* steps, char* ws,
+                         const CadLayout& C, hipStream_t s) {
+  const double b = p->basis.b;
+  int it = 0;
+  while (it < maxit) {
+    ++it;
+    double r[4];
+    {
+      Timed t(p, s, K_SELECT);
+      HIP_TRY(launch_recentre_sums(p->dtype, n, x, y, z, w, c, 1.0 / b, p->basis.alpha, p->amode,
+                                   1e-9 * b, (double*)(ws + C.mom), (double*)(ws + C.res), s));
+    }
+    HIP_TRY(hipMemcpyAsync(r, ws + C.res, sizeof(r), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!(r[0] > 0.0)) break;
+    double step2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double cn = r[1 + k] / r[0];
+      step2 += (cn - c[k]) * (cn - c[k]);
+      c[k] = cn;
+    }
+    if (std::sqrt(step2) <= tol * b) break;
+  }
+  if (steps) *steps = it;
+  return SCF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2043,7 +2126,8 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
   if (n < 0 || nint < 0) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nint >= 0");
   if (!(cfg->eta > 0.0) || !(cfg->dt_max > 0.0) || !(cfg->frac > 0.0 && cfg->frac <= 1.0) ||
       cfg->refresh_every < 1 || cfg->n_samples_tdyn < 0 || cfg->ns_max < 1 ||
-      cfg->ns_max > SCF_MAX_SAMPLES || (cfg->n_samples_tdyn > 0 && !(cfg->c_dyn > 0.0)))
+      cfg->ns_max > SCF_MAX_SAMPLES || (cfg->n_samples_tdyn > 0 && !(cfg->c_dyn > 0.0)) ||
+      (cfg->recentre != 0 && cfg->recentre != 1))
     return fail(SCF_ERR_INVALID_ARG, "invalid cadence parameters");
   if (!host || host->ncomp < 1)
     return fail(SCF_ERR_INVALID_ARG, "the cadence needs a host potential (its tidal tensor sets the interval)");
@@ -2108,6 +2192,7 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
       if (st != SCF_OK) return st;
       int64_t nchanged = 0;
       const bool complete = state->since + 1 >= cfg->refresh_every;
+      double dx[3] = {0.0, 0.0, 0.0}, dv[3] = {0.0, 0.0, 0.0};
       if (complete) {
         // count of changed weights (no compaction), then the full sums
         DeltaSnaps none;
@@ -2115,8 +2200,27 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
         HIP_TRY(launch_delta_compact(p->dtype, n, w, wnew, none, (int32_t*)(wsp + C.cnt),
                                      (int64_t*)(wsp + C.off), (int64_t*)(wsp + C.total), nullptr, 0, s));
         HIP_TRY(hipMemcpyAsync(&nchanged, wsp + C.total, 8, hipMemcpyDeviceToHost, s));
+        if (cfg->recentre) {
+          // frame origin to the a_000 maximum of the selected particles:
+          // positions, earlier samples and the centre orbit shift with it
+          st = recentre_impl(p, n, x, y, z, wnew, dx, 1e-6, 100, nullptr, wsp, C, s);
+          if (st != SCF_OK) return st;
+          HIP_TRY(launch_shift3(p->dtype, n, x, y, z, dx, s));
+          for (int j = 0; j + 1 < ns; ++j)
+            HIP_TRY(launch_shift3(p->dtype, n, (void*)sx[j], (void*)sy[j], (void*)sz[j], dx, s));
+          for (int k = 0; k < 3; ++k) R[k] += dx[k];
+        }
         st = complete_impl<Rt>(p, n, ns, sx, sy, sz, wnew, coef, wsp, C, s);
         if (st != SCF_OK) return st;
+        if (cfg->recentre) {
+          // frame velocity to the core velocity of the new potential
+          double core[5];
+          st = core_impl<Rt>(p, n, x, y, z, vx, vy, vz, m, wnew, coef, core, wsp, C, s);
+          if (st != SCF_OK) return st;
+          for (int k = 0; k < 3; ++k) dv[k] = core[1 + k];
+          HIP_TRY(launch_shift3(p->dtype, n, vx, vy, vz, dv, s));
+          for (int k = 0; k < 3; ++k) V[k] += dv[k];
+        }
         state->since = 0;
       } else {
         st = delta_impl<Rt>(p, n, ns, sx, sy, sz, w, wnew, coef, &nchanged, wsp, C, s);
@@ -2145,6 +2249,10 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
         e.rx = sel.rx;
         e.rhm = sel.rhm;
         e.mbound = sel.mbound;
+        for (int k = 0; k < 3; ++k) {
+          e.dx[k] = dx[k];
+          e.dv[k] = dv[k];
+        }
       }
     }
     return SCF_OK;
@@ -2158,37 +2266,6 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
 }
 
 
-}  // extern "C"
-
-namespace {
-
-// rho_SCF (Eq. total_dens) of coef at n points into rho: the field pass's psi
-// with density-scaled weights, times the radial factor
-template <typename R>
-scf_status density_impl(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
-                        const double* coef, void* rho, char* ws, const CadLayout& C, hipStream_t s) {
-  void* W = ws + C.L.W;
-  {
-    Timed t(p, s, K_MAKE_W);
-    HIP_TRY(launch_make_w(p->dtype, coef, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_fw, W, s));
-    HIP_TRY(launch_scale_w(p->dtype, W, p->d_kden, p->lmax, p->nmaxc, s));
-  }
-  HostParams<R> none;
-  std::memset(&none, 0, sizeof(none));
-  const size_t nr = (size_t)n * p->rs;
-  char* acc = ws + C.acc;
-  scf_status st = run_field<R>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, acc,
-                               acc + nr, acc + 2 * nr, rho, W, none, nullptr, 0, 0.0, 0.0, s);
-  if (st != SCF_OK) return st;
-  Timed t(p, s, K_SELECT);
-  HIP_TRY(launch_density_factor(p->dtype, n, x, y, z, 1.0 / p->basis.b, 1.0 / p->basis.alpha,
-                                p->amode, rho, s));
-  return SCF_OK;
-}
-
-}  // namespace
-
-extern "C" {
 
 scf_status scf_density(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
                        const double* coef, void* rho, void* ws, size_t ws_bytes, void* stream) {
@@ -2216,31 +2293,24 @@ scf_status scf_core(scf_plan* p, int64_t n, const void* x, const void* y, const 
   if (cs != SCF_OK) return cs;
   const CadLayout C = cad_layout(p, n, 1);
   hipStream_t s = (hipStream_t)stream;
-  char* wsp = (char*)ws;
-  void* rho = wsp + C.pot;
-  scf_status st = p->dtype == SCF_F32 ? density_impl<float>(p, n, x, y, z, coef, rho, wsp, C, s)
-                                      : density_impl<double>(p, n, x, y, z, coef, rho, wsp, C, s);
-  if (st != SCF_OK) return st;
-  double r[4];
-  {
-    Timed t(p, s, K_SELECT);
-    HIP_TRY(launch_core_moments(p->dtype, n, x, y, z, vx, vy, vz, m, w, rho, 0, 0.0,
-                                (double*)(wsp + C.mom), (double*)(wsp + C.res), s));
-  }
-  HIP_TRY(hipMemcpyAsync(r, wsp + C.res, sizeof(r), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const double rc2 = r[1] > 0.0 ? r[0] / r[1] : 0.0;
-  {
-    Timed t(p, s, K_SELECT);
-    HIP_TRY(launch_core_moments(p->dtype, n, x, y, z, vx, vy, vz, m, w, rho, 1, rc2,
-                                (double*)(wsp + C.mom), (double*)(wsp + C.res), s));
-  }
-  HIP_TRY(hipMemcpyAsync(r, wsp + C.res, sizeof(r), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  out[0] = std::sqrt(rc2);
-  for (int k = 0; k < 3; ++k) out[1 + k] = r[3] > 0.0 ? r[k] / r[3] : 0.0;
-  out[4] = r[3];
-  return SCF_OK;
+  return p->dtype == SCF_F32
+             ? core_impl<float>(p, n, x, y, z, vx, vy, vz, m, w, coef, out, (char*)ws, C, s)
+             : core_impl<double>(p, n, x, y, z, vx, vy, vz, m, w, coef, out, (char*)ws, C, s);
+}
+
+scf_status scf_recentre(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                        const void* w, double* centre, double tol, int32_t maxit, int32_t* steps,
+                        void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !centre) return fail(SCF_ERR_INVALID_ARG, "plan and centre must be non-null");
+  if (n < 0 || maxit < 0 || !(tol >= 0.0))
+    return fail(SCF_ERR_INVALID_ARG, "need n >= 0, maxit >= 0 and tol >= 0");
+  if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(w)))
+    return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
+  scf_status cs = check_cadence_ws(p, n, 1, ws, ws_bytes);
+  if (cs != SCF_OK) return cs;
+  const CadLayout C = cad_layout(p, n, 1);
+  return recentre_impl(p, n, x, y, z, w, centre, tol, maxit, steps, (char*)ws, C,
+                       (hipStream_t)stream);
 }
 
 }  // extern "C"

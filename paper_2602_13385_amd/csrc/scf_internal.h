@@ -221,5 +221,13 @@ hipError_t launch_core_moments(int dtype, int64_t n, const void* x, const void* 
                                const void* vx, const void* vy, const void* vz, const void* m,
                                const void* w, const void* rho, int mode, double r2max,
                                double* part, double* res, hipStream_t s);
+// frame centre: fixed-order double sums of (w omega, w omega x, y, z) about c
+// into part[nblk][4] and res[4]
+hipError_t launch_recentre_sums(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                                const void* w, const double* c, double binv, double alpha,
+                                int amode, double rmin, double* part, double* res, hipStream_t s);
+// a_k -= d[k] on three arrays of n
+hipError_t launch_shift3(int dtype, int64_t n, void* a0, void* a1, void* a2, const double* d,
+                         hipStream_t s);
 
 }  // namespace scf

@@ -366,6 +366,67 @@ __global__ void __launch_bounds__(256) moments_sum_kernel(const double* __restri
   if (threadIdx.x < 4) res[threadIdx.x] = red[threadIdx.x][0];
 }
 
+// ---- frame centre (Sec. 2.1) ------------------------------------------------
+// Block sums (fixed order) of w omega, w omega x, w omega y, w omega z with
+// omega = t (1 + t)^(-alpha-1) / r^2, t = (r/b)^(1/alpha), r = |x - c|, over
+// the particles with w > 0 and r > rmin; all in double precision.
+template <typename R>
+__global__ void __launch_bounds__(256) recentre_sums_kernel(int64_t n, const R* __restrict__ x,
+                                                            const R* __restrict__ y,
+                                                            const R* __restrict__ z,
+                                                            const R* __restrict__ w, double cx,
+                                                            double cy, double cz, double binv,
+                                                            double alpha, int amode, double rmin,
+                                                            double* __restrict__ out) {
+#pragma clang fp contract(off)
+  __shared__ double red[4][256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < n && w[i] > R(0)) {
+    const double xi = x[i], yi = y[i], zi = z[i];
+    const double dx = xi - cx, dy = yi - cy, dz = zi - cz;
+    const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+    if (r > rmin) {
+      const double s = r * binv;
+      double om;
+      if (amode == 0) {
+        om = s / ((1.0 + s) * (1.0 + s) * (r * r));
+      } else if (amode == 1) {
+        const double t = s * s;
+        om = t / ((1.0 + t) * sqrt(1.0 + t) * (r * r));
+      } else {
+        const double t = pow(s, 1.0 / alpha);
+        om = t * pow(1.0 + t, -alpha - 1.0) / (r * r);
+      }
+      om *= (double)w[i];
+      q[0] = om;
+      q[1] = om * xi;
+      q[2] = om * yi;
+      q[3] = om * zi;
+    }
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = q[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[(int64_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// a -= d for three arrays (a frame shift of positions or velocities)
+template <typename R>
+__global__ void __launch_bounds__(256) shift3_kernel(int64_t n, R* __restrict__ a0, R* __restrict__ a1,
+                                                     R* __restrict__ a2, double d0, double d1,
+                                                     double d2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  a0[i] = R((double)a0[i] - d0);
+  a1[i] = R((double)a1[i] - d1);
+  a2[i] = R((double)a2[i] - d2);
+}
+
 inline unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -489,6 +550,36 @@ hipError_t launch_core_moments(int dtype, int64_t n, const void* x, const void* 
           (const double*)rho, mode, r2max, part);
   }
   moments_sum_kernel<<<1, 256, 0, s>>>(part, nblk, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_recentre_sums(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                                const void* w, const double* c, double binv, double alpha,
+                                int amode, double rmin, double* part, double* res, hipStream_t s) {
+  const int64_t nblk = n > 0 ? (int64_t)blocks_of(n) : 0;
+  if (n > 0) {
+    if (dtype == 0)
+      recentre_sums_kernel<float><<<blocks_of(n), 256, 0, s>>>(
+          n, (const float*)x, (const float*)y, (const float*)z, (const float*)w, c[0], c[1], c[2],
+          binv, alpha, amode, rmin, part);
+    else
+      recentre_sums_kernel<double><<<blocks_of(n), 256, 0, s>>>(
+          n, (const double*)x, (const double*)y, (const double*)z, (const double*)w, c[0], c[1],
+          c[2], binv, alpha, amode, rmin, part);
+  }
+  moments_sum_kernel<<<1, 256, 0, s>>>(part, nblk, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift3(int dtype, int64_t n, void* a0, void* a1, void* a2, const double* d,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (dtype == 0)
+    shift3_kernel<float><<<blocks_of(n), 256, 0, s>>>(n, (float*)a0, (float*)a1, (float*)a2, d[0],
+                                                      d[1], d[2]);
+  else
+    shift3_kernel<double><<<blocks_of(n), 256, 0, s>>>(n, (double*)a0, (double*)a1, (double*)a2,
+                                                       d[0], d[1], d[2]);
   return hipGetLastError();
 }
 

@@ -57,7 +57,7 @@ class CHost(C.Structure):
 class CCadence(C.Structure):
     _fields_ = [("eta", C.c_double), ("dt_max", C.c_double), ("frac", C.c_double),
                 ("c_dyn", C.c_double), ("refresh_every", C.c_int32), ("n_samples_tdyn", C.c_int32),
-                ("ns_max", C.c_int32), ("pad", C.c_int32)]
+                ("ns_max", C.c_int32), ("recentre", C.c_int32)]
 
 
 class CCadenceState(C.Structure):
@@ -69,7 +69,7 @@ class CIntervalLog(C.Structure):
     _fields_ = [("dt_int", C.c_double), ("nsub", C.c_int32), ("nsamples", C.c_int32),
                 ("complete", C.c_int32), ("pad", C.c_int32), ("nbound", C.c_int64),
                 ("nchanged", C.c_int64), ("rx", C.c_double), ("rhm", C.c_double),
-                ("mbound", C.c_double)]
+                ("mbound", C.c_double), ("dx", C.c_double * 3), ("dv", C.c_double * 3)]
 
 
 MAX_SAMPLES = 16
@@ -88,10 +88,12 @@ class Cadence:
     n_samples_tdyn: int = 0
     c_dyn: float = C_DYN
     ns_max: int = 8
+    recentre: bool = False
 
     def c(self):
         return CCadence(float(self.eta), float(self.dt_max), float(self.frac), float(self.c_dyn),
-                        int(self.refresh_every), int(self.n_samples_tdyn), int(self.ns_max), 0)
+                        int(self.refresh_every), int(self.n_samples_tdyn), int(self.ns_max),
+                        1 if self.recentre else 0)
 
 
 def _state_dict(st):
@@ -151,6 +153,8 @@ SIGNATURES = {
     "scf_density": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "scf_core": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, _vp,
                            C.c_size_t, _vp]),
+    "scf_recentre": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _dp, C.c_double, C.c_int32,
+                               C.POINTER(C.c_int32), _vp, C.c_size_t, _vp]),
     "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
     "scf_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -535,7 +539,8 @@ class Plan:
                                 _stream()))
         log = [{"dt_int": e.dt_int, "nsub": e.nsub, "nsamples": e.nsamples,
                 "kind": "complete" if e.complete else "intermediate", "nbound": e.nbound,
-                "nchanged": e.nchanged, "rx": e.rx, "rhm": e.rhm, "mbound": e.mbound}
+                "nchanged": e.nchanged, "rx": e.rx, "rhm": e.rhm, "mbound": e.mbound,
+                "dx": np.array(e.dx[:]), "dv": np.array(e.dv[:])}
                for e in logs[:int(nint)]]
         return np.array(cen[:]), _state_dict(cs), log
 
@@ -560,3 +565,16 @@ class Plan:
         _check(lib().scf_core(self._h, n, *[_ptr(t) for t in st], _ptr(m), _ptr(w), _ptr(coef),
                               C.cast(out, _dp), _ptr(ws), ws.numel(), _stream()))
         return out[0], np.array(out[1:4]), out[4]
+
+    def recentre(self, x, y, z, w, centre=(0.0, 0.0, 0.0), tol=1e-6, maxit=100):
+        """Frame centre (Sec. 2.1): the a_000 maximum of the particles with
+        w > 0, searched from centre.  Returns (centre (3,), steps)."""
+        self._check_arrays(x, y, z, w)
+        n = x.numel()
+        c = (C.c_double * 3)(*[float(v) for v in centre])
+        steps = C.c_int32()
+        ws = self.cadence_workspace(n, 1, device=x.device)
+        _check(lib().scf_recentre(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(w), C.cast(c, _dp),
+                                  float(tol), int(maxit), C.byref(steps), _ptr(ws), ws.numel(),
+                                  _stream()))
+        return np.array(c[:]), int(steps.value)
