@@ -229,7 +229,11 @@ scf_status scf_tidal_norm(const scf_host* host, const double* pos, double* norm)
  * the selected particles (scf_recentre from the current origin, tol 1e-6 b,
  * at most 100 steps; positions, samples and the centre orbit's R shift), then
  * computes the coefficients, then moves the frame velocity to the core
- * velocity of the new potential (scf_core; velocities and V shift). */
+ * velocity of the new potential (scf_core; velocities and V shift).  With
+ * retune, a complete refresh (after any recentring) also sets the plan's
+ * alpha and b to scf_tune_basis's result over the selected particles before
+ * the coefficients are computed, so the coefficients and the plan's basis
+ * change together. */
 #define SCF_MAX_SAMPLES 16
 typedef struct {
   double eta;             /* Eq. tidal_timestep parameter (1/400 in the paper), > 0 */
@@ -242,6 +246,10 @@ typedef struct {
   int32_t ns_max;         /* most samples per interval, 1..SCF_MAX_SAMPLES */
   int32_t recentre;       /* 1: at complete refreshes move the frame to the a_000 maximum
                              and the core velocity (scf_recentre, scf_core) */
+  int32_t retune;         /* 1: at complete refreshes retune alpha and b (scf_tune_basis;
+                             the plan's basis changes) */
+  int32_t pad;
+  double alpha_min;       /* lower bound of alpha for retune, in (0, 1) */
 } scf_cadence;
 
 /* Cadence state carried between calls (host, in/out). */
@@ -262,6 +270,7 @@ typedef struct {
   int64_t nbound, nchanged; /* bound particles; particles whose weight changed */
   double rx, rhm, mbound;
   double dx[3], dv[3];    /* frame shift applied at this interval's end (recentre) */
+  double alpha, b;        /* the plan's basis after this interval (retune) */
 } scf_interval_log;
 
 /* Workspace bytes for scf_select, scf_coeffs_delta, scf_cadence_init and
@@ -353,6 +362,30 @@ scf_status scf_core(scf_plan* plan, int64_t n, const void* x, const void* y, con
 scf_status scf_recentre(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
                         const void* w, double* centre, double tol, int32_t maxit, int32_t* steps,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* Basis parameters (Sec. 2, Eq. u00 and the text after it): alpha and b are
+ * tuned so that the zeroth mode matches the cluster potential.  About the
+ * origin, a_000 = Y_00 sum_k w_k f(r_k) / sqrt(N_00) with
+ * f = (1 + (r/b)^(1/alpha))^(-alpha) and the energy norm
+ * N_00 = b alpha B(alpha + 2, alpha) / (4 pi G) (B the Beta function); the
+ * basis is orthonormal in that norm, so a_000 is the projection of the
+ * cluster potential on the unit zeroth mode and its maximum picks the zeroth
+ * mode closest to it.  scf_tune_basis maximises it over alpha in
+ * [alpha_min, 1] and b > 0 for the particles with w > 0: the best point of a
+ * 7 x 17 grid in (alpha, ln b) about the start, then a Nelder-Mead search
+ * with alpha = alpha_min + (1 - alpha_min) sin^2 u; each value is a
+ * double-precision device reduction.  alpha_b (host, 2 doubles): in, the
+ * start (alpha, b); out, the maximum; a000 (host, nullable) its value.
+ * Blocks; workspace of scf_cadence_workspace_size(plan, n, 1).
+ * scf_plan_set_basis replaces a plan's alpha and b (nmax, lmax, G and dtype
+ * stay): the basis tables are recomputed and copied to the device after the
+ * device has finished all queued work.  Coefficients computed before the
+ * change belong to the old basis.  scf_plan_get_basis reads the current one. */
+scf_status scf_tune_basis(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
+                          const void* w, double alpha_min, double* alpha_b, double* a000,
+                          void* ws, size_t ws_bytes, void* stream);
+scf_status scf_plan_set_basis(scf_plan* plan, double alpha, double b);
+scf_status scf_plan_get_basis(const scf_plan* plan, scf_basis* out);
 
 /* Launch configuration.  The coefficient kernel has several compiled
  * variants (lanes per particle in the basis phase, waves per block).

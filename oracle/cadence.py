@@ -160,13 +160,16 @@ def initial_refresh(B, state, m, frac, key_dtype=np.float64):
 
 def evolve(B, H, state, m, centre, coef, w, nint, *, eta, dt_max, frac=0.999,
            refresh_every=5, n_samples_tdyn=0, c_dyn=C_DYN, ns_max=8, since=0, mbound=0.0,
-           rhm=0.0, key_dtype=np.float64, recentre=False):
+           rhm=0.0, key_dtype=np.float64, recentre=False, retune=False, alpha_min=0.25):
     """nint integration intervals of the cadence.  Returns the state, centre,
     coefficients, weights, the cadence state (since, mbound, rhm) and one log
     entry per interval.  With recentre, a complete refresh first moves the
     frame origin to the a_000 maximum of the selected particles (Sec. 2.1;
     positions, samples and the centre shift), computes the coefficients, then
-    moves the frame velocity to the core velocity of the new potential."""
+    moves the frame velocity to the core velocity of the new potential.  With
+    retune, the complete refresh (after any recentring) first sets the basis
+    (alpha, b) to the a_000 maximum over the selected particles; the basis in
+    force at the end is returned as the last item."""
     st = np.array(state, dtype=np.float64, copy=True)
     cen = np.array(centre, dtype=np.float64, copy=True)
     coef = np.array(coef, dtype=np.float64, copy=True)
@@ -195,6 +198,9 @@ def evolve(B, H, state, m, centre, coef, w, nint, *, eta, dt_max, frac=0.999,
                 st[:3] -= dx[:, None]
                 snaps = [s - dx[:, None] for s in snaps[:-1]] + [st[:3].copy()]
                 cen[:3] += dx
+            if retune:
+                a, b, _ = F.tune_basis(st[:3], w_new, B.alpha, B.b, B.G, alpha_min)
+                B = O.basis(B.nmax, B.lmax, alpha=a, b=b, G=B.G)
             coef = complete_refresh(B, snaps, w_new)
             if recentre:
                 _, dv, _ = O.core(B, coef, st, m, w_new)
@@ -209,5 +215,8 @@ def evolve(B, H, state, m, centre, coef, w, nint, *, eta, dt_max, frac=0.999,
         log.append({"dt_int": dti, "nsub": nsub, "nsamples": ns, "kind": kind,
                     "nbound": info["nbound"], "nchanged": nchanged, "rx": info["rx"],
                     "rhm": rhm, "mbound": mbound, "emargin": info["emargin"],
-                    "gap": info["gap"], "ns_ratio": ratio, "dx": dx, "dv": dv})
+                    "gap": info["gap"], "ns_ratio": ratio, "dx": dx, "dv": dv,
+                    "alpha": B.alpha, "b": B.b})
+    if retune:
+        return st, cen, coef, w, (since, mbound, rhm), log, B
     return st, cen, coef, w, (since, mbound, rhm), log

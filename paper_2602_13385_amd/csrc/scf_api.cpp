@@ -517,6 +517,80 @@ scf_status run_field(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx
   return SCF_OK;
 }
 
+// Basis tables of a plan for (alpha, b) (and its nmax, lmax, G): recurrence
+// constants, per-coefficient sign and scale, density constants; uploaded to
+// the plan's device buffers (allocated on the first call).
+hipError_t fill_tables(scf_plan* p, const scf_basis* basis) {
+  p->basis = *basis;
+  p->amode = basis->alpha == 1.0 ? 0 : (basis->alpha == 0.5 ? 1 : 2);
+  const int L1 = p->lmax + 1, NW = p->nmaxc + 1;
+  // Legendre table: b_{l,m} at [m L1 + l] (b_{m,m} = -1 starts the order
+  // recurrence of the field pass), then the integers 0..lmax at [L1 L1 + k]
+  std::vector<double> brad((size_t)L1 * NW, 0.0), bang((size_t)L1 * L1 + L1, 0.0);
+  for (int l = 0; l <= p->lmax; ++l) {
+    const double lam = (2.0 * l + 1.0) * basis->alpha + 0.5;
+    for (int n = 0; n <= p->nmaxc; ++n) brad[(size_t)l * NW + n] = gegen_beta(n, lam);
+  }
+  for (int m = 0; m <= p->lmax; ++m)
+    for (int l = 0; l <= p->lmax; ++l) bang[(size_t)m * L1 + l] = l == m ? -1.0 : legendre_gamma(l, m);
+  for (int k = 0; k <= p->lmax; ++k) bang[(size_t)L1 * L1 + k] = k;
+  const int L2 = L1 * L1;
+  p->h_cs.assign(p->T, 0.0);
+  p->h_fw.assign(p->T, 0.0);
+  for (int n = 0; n <= p->nmax; ++n) {
+    for (int l = 0; l <= p->lmax; ++l) {
+      const double lam = (2.0 * l + 1.0) * basis->alpha + 0.5;
+      const double Nnl = norm_nl(basis->alpha, basis->b, basis->G, n, l);
+      const double kn = gegen_lead(n, lam);
+      for (int j = 0; j <= 2 * l; ++j) {
+        const int m = (j + 1) / 2;
+        const double kappa = -(kn / std::sqrt(Nnl)) * ylm_norm(l, m) * ((m & 1) ? -1.0 : 1.0) *
+                             legendre_rho(l, m);
+        const bool sin_part = j > 0 && (j % 2 == 0);
+        const double sigma = sin_part ? 1.0 : -1.0;
+        const double w = j == 0 ? 1.0 : (sin_part ? -2.0 : 2.0);
+        const int64_t t = (int64_t)n * L2 + l * l + j;
+        p->h_cs[t] = sigma * kappa;
+        p->h_fw[t] = w * kappa;
+      }
+    }
+  }
+  // device copies: allocated on the first call, overwritten afterwards
+  auto upload_real = [&](const std::vector<double>& v, void** dst) -> hipError_t {
+    if (!*dst) {
+      hipError_t e = hipMalloc(dst, v.size() * p->rs + 16);
+      if (e != hipSuccess) return e;
+    }
+    if (p->rs == 4) {
+      std::vector<float> f(v.begin(), v.end());
+      return hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    }
+    return hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+  };
+  hipError_t e = upload_real(brad, &p->d_beta_rad);
+  if (e == hipSuccess) e = upload_real(bang, &p->d_beta_ang);
+  if (e == hipSuccess && !p->d_cs) e = hipMalloc((void**)&p->d_cs, p->T * 8);
+  if (e == hipSuccess) e = hipMemcpy(p->d_cs, p->h_cs.data(), p->T * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p->d_fw) e = hipMalloc((void**)&p->d_fw, p->T * 8);
+  if (e == hipSuccess) e = hipMemcpy(p->d_fw, p->h_fw.data(), p->T * 8, hipMemcpyHostToDevice);
+  {
+    // density basis: the radial Laplacian of s^l (1 + s^(1/alpha))^(-p) C_n^lambda(xi)
+    // is -K_nl s^(1/alpha - 2) (1 + s^(1/alpha))^(-2) times the same function,
+    // K_nl = [n(n + 2 lambda) + p(p + 1)] / alpha^2, p = alpha (2l + 1)
+    std::vector<double> kd((size_t)L1 * NW, 0.0);
+    const double a = basis->alpha;
+    for (int l = 0; l <= p->lmax; ++l)
+      for (int n = 0; n <= p->nmax; ++n) {
+        const double pp = a * (2.0 * l + 1.0), lam = pp + 0.5;
+        const double K = (n * (n + 2.0 * lam) + pp * (pp + 1.0)) / (a * a);
+        kd[(size_t)l * NW + n] = -K / (4.0 * M_PI * basis->G * basis->b * basis->b);
+      }
+    if (e == hipSuccess && !p->d_kden) e = hipMalloc((void**)&p->d_kden, kd.size() * 8);
+    if (e == hipSuccess) e = hipMemcpy(p->d_kden, kd.data(), kd.size() * 8, hipMemcpyHostToDevice);
+  }
+  return e;
+}
+
 // ---------------------------------------------------------------------------
 // adjoint
 // ---------------------------------------------------------------------------
@@ -847,14 +921,12 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
   int device = 0;
   HIP_TRY(hipGetDevice(&device));
   scf_plan* p = new scf_plan();
-  p->basis = *basis;
   p->dtype = dtype;
   p->device = device;
   p->nmax = basis->nmax;
   p->lmax = basis->lmax;
   p->nmaxc = eng->nmaxc();
   p->T = scf_ncoef(basis->nmax, basis->lmax);
-  p->amode = basis->alpha == 1.0 ? 0 : (basis->alpha == 0.5 ? 1 : 2);
   p->eng = eng;
   p->rs = eng->real_size();
   {
@@ -864,68 +936,7 @@ scf_status scf_plan_create(scf_plan** out, const scf_basis* basis, int32_t dtype
     for (int v = 0; v < eng->coef_variants() && v < 8; ++v) p->resident[v] = eng->max_resident_units(v);
     p->gamma_resident = eng->gamma_resident_units();
   }
-  const int L1 = p->lmax + 1, NW = p->nmaxc + 1;
-  // Legendre table: b_{l,m} at [m L1 + l] (b_{m,m} = -1 starts the order
-  // recurrence of the field pass), then the integers 0..lmax at [L1 L1 + k]
-  std::vector<double> brad((size_t)L1 * NW, 0.0), bang((size_t)L1 * L1 + L1, 0.0);
-  for (int l = 0; l <= p->lmax; ++l) {
-    const double lam = (2.0 * l + 1.0) * basis->alpha + 0.5;
-    for (int n = 0; n <= p->nmaxc; ++n) brad[(size_t)l * NW + n] = gegen_beta(n, lam);
-  }
-  for (int m = 0; m <= p->lmax; ++m)
-    for (int l = 0; l <= p->lmax; ++l) bang[(size_t)m * L1 + l] = l == m ? -1.0 : legendre_gamma(l, m);
-  for (int k = 0; k <= p->lmax; ++k) bang[(size_t)L1 * L1 + k] = k;
-  const int L2 = L1 * L1;
-  p->h_cs.assign(p->T, 0.0);
-  p->h_fw.assign(p->T, 0.0);
-  for (int n = 0; n <= p->nmax; ++n) {
-    for (int l = 0; l <= p->lmax; ++l) {
-      const double lam = (2.0 * l + 1.0) * basis->alpha + 0.5;
-      const double Nnl = norm_nl(basis->alpha, basis->b, basis->G, n, l);
-      const double kn = gegen_lead(n, lam);
-      for (int j = 0; j <= 2 * l; ++j) {
-        const int m = (j + 1) / 2;
-        const double kappa = -(kn / std::sqrt(Nnl)) * ylm_norm(l, m) * ((m & 1) ? -1.0 : 1.0) *
-                             legendre_rho(l, m);
-        const bool sin_part = j > 0 && (j % 2 == 0);
-        const double sigma = sin_part ? 1.0 : -1.0;
-        const double w = j == 0 ? 1.0 : (sin_part ? -2.0 : 2.0);
-        const int64_t t = (int64_t)n * L2 + l * l + j;
-        p->h_cs[t] = sigma * kappa;
-        p->h_fw[t] = w * kappa;
-      }
-    }
-  }
-  auto upload_real = [&](const std::vector<double>& v, void** dst) -> hipError_t {
-    hipError_t e = hipMalloc(dst, v.size() * p->rs + 16);
-    if (e != hipSuccess) return e;
-    if (p->rs == 4) {
-      std::vector<float> f(v.begin(), v.end());
-      return hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
-    }
-    return hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
-  };
-  hipError_t e = upload_real(brad, &p->d_beta_rad);
-  if (e == hipSuccess) e = upload_real(bang, &p->d_beta_ang);
-  if (e == hipSuccess) e = hipMalloc((void**)&p->d_cs, p->T * 8);
-  if (e == hipSuccess) e = hipMemcpy(p->d_cs, p->h_cs.data(), p->T * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc((void**)&p->d_fw, p->T * 8);
-  if (e == hipSuccess) e = hipMemcpy(p->d_fw, p->h_fw.data(), p->T * 8, hipMemcpyHostToDevice);
-  {
-    // density basis: the radial Laplacian of s^l (1 + s^(1/alpha))^(-p) C_n^lambda(xi)
-    // is -K_nl s^(1/alpha - 2) (1 + s^(1/alpha))^(-2) times the same function,
-    // K_nl = [n(n + 2 lambda) + p(p + 1)] / alpha^2, p = alpha (2l + 1)
-    std::vector<double> kd((size_t)L1 * NW, 0.0);
-    const double a = basis->alpha;
-    for (int l = 0; l <= p->lmax; ++l)
-      for (int n = 0; n <= p->nmax; ++n) {
-        const double pp = a * (2.0 * l + 1.0), lam = pp + 0.5;
-        const double K = (n * (n + 2.0 * lam) + pp * (pp + 1.0)) / (a * a);
-        kd[(size_t)l * NW + n] = -K / (4.0 * M_PI * basis->G * basis->b * basis->b);
-      }
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_kden, kd.size() * 8);
-    if (e == hipSuccess) e = hipMemcpy(p->d_kden, kd.data(), kd.size() * 8, hipMemcpyHostToDevice);
-  }
+  hipError_t e = fill_tables(p, basis);
   if (e != hipSuccess) {
     scf_plan_destroy(p);
     return fail(SCF_ERR_HIP, "plan allocation failed: %s", hipGetErrorString(e));
@@ -1961,6 +1972,125 @@ scf_status recentre_impl(scf_plan* p, int64_t n, const void* x, const void* y, c
   return SCF_OK;
 }
 
+// energy norm of the zeroth mode, b alpha B(alpha + 2, alpha) / (4 pi G)
+double n00_closed(double alpha, double b, double G) {
+  const double beta = std::exp(std::lgamma(alpha + 2.0) + std::lgamma(alpha) - std::lgamma(2.0 * alpha + 2.0));
+  return b * alpha * beta / (4.0 * M_PI * G);
+}
+
+// (alpha, b) maximising a_000 of the particles with w > 0 about the origin,
+// alpha in [amin, 1]: the best point of a coarse grid, then Nelder-Mead in
+// (u, ln b) with alpha = amin + (1 - amin) sin^2 u (no bound to handle).  Each
+// objective value is one device reduction.  ab: in, the start; out, the result.
+scf_status tune_impl(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                     const void* w, double amin, double* ab, double* best_val, char* ws,
+                     const CadLayout& C, hipStream_t s) {
+  const double G = p->basis.G;
+  auto eval = [&](double alpha, double b, double* out) -> scf_status {
+    double r[4];
+    {
+      Timed t(p, s, K_SELECT);
+      HIP_TRY(launch_a000_sum(p->dtype, n, x, y, z, w, alpha, 1.0 / b, (double*)(ws + C.mom),
+                              (double*)(ws + C.res), s));
+    }
+    HIP_TRY(hipMemcpyAsync(r, ws + C.res, sizeof(r), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = r[0] / std::sqrt(4.0 * M_PI * n00_closed(alpha, b, G));
+    return SCF_OK;
+  };
+  auto alpha_of = [&](double u) { const double q = std::sin(u); return amin + (1.0 - amin) * q * q; };
+  const double lb0 = std::log(ab[1]);
+  double fbest = -1.0, ubest = 0.0, lbbest = lb0;
+  for (int ia = 0; ia < 7; ++ia) {
+    const double alpha = amin + (1.0 - amin) * ia / 6.0;
+    for (int ib = 0; ib < 17; ++ib) {
+      const double lb = lb0 - 4.0 + 0.5 * ib;
+      double f;
+      scf_status st = eval(alpha, std::exp(lb), &f);
+      if (st != SCF_OK) return st;
+      if (f > fbest) {
+        fbest = f;
+        ubest = std::asin(std::sqrt(std::min(1.0, (alpha - amin) / (1.0 - amin))));
+        lbbest = lb;
+      }
+    }
+  }
+  // Nelder-Mead (maximisation) on (u, ln b)
+  double P[3][2] = {{ubest, lbbest}, {ubest + 0.15, lbbest}, {ubest, lbbest + 0.15}};
+  double F[3];
+  for (int k = 0; k < 3; ++k) {
+    scf_status st = eval(alpha_of(P[k][0]), std::exp(P[k][1]), &F[k]);
+    if (st != SCF_OK) return st;
+  }
+  for (int it = 0; it < 600; ++it) {
+    // order: 0 best, 2 worst
+    for (int a = 0; a < 2; ++a)
+      for (int b2 = 0; b2 < 2 - a; ++b2)
+        if (F[b2] < F[b2 + 1]) {
+          std::swap(F[b2], F[b2 + 1]);
+          std::swap(P[b2][0], P[b2 + 1][0]);
+          std::swap(P[b2][1], P[b2 + 1][1]);
+        }
+    double size = 0.0;
+    for (int k = 1; k < 3; ++k)
+      size = std::max(size, std::max(std::fabs(P[k][0] - P[0][0]), std::fabs(P[k][1] - P[0][1])));
+    if (size < 1e-10) break;
+    const double c0 = 0.5 * (P[0][0] + P[1][0]), c1 = 0.5 * (P[0][1] + P[1][1]);
+    auto at = [&](double t, double* q) { q[0] = c0 + t * (P[2][0] - c0); q[1] = c1 + t * (P[2][1] - c1); };
+    double xr[2], fr;
+    at(-1.0, xr);
+    scf_status st = eval(alpha_of(xr[0]), std::exp(xr[1]), &fr);
+    if (st != SCF_OK) return st;
+    if (fr > F[0]) {
+      double xe[2], fe;
+      at(-2.0, xe);
+      st = eval(alpha_of(xe[0]), std::exp(xe[1]), &fe);
+      if (st != SCF_OK) return st;
+      if (fe > fr) {
+        P[2][0] = xe[0]; P[2][1] = xe[1]; F[2] = fe;
+      } else {
+        P[2][0] = xr[0]; P[2][1] = xr[1]; F[2] = fr;
+      }
+    } else if (fr > F[1]) {
+      P[2][0] = xr[0]; P[2][1] = xr[1]; F[2] = fr;
+    } else {
+      double xc[2], fc;
+      at(fr > F[2] ? -0.5 : 0.5, xc);
+      st = eval(alpha_of(xc[0]), std::exp(xc[1]), &fc);
+      if (st != SCF_OK) return st;
+      if (fc > std::max(fr, F[2])) {
+        P[2][0] = xc[0]; P[2][1] = xc[1]; F[2] = fc;
+      } else {
+        for (int k = 1; k < 3; ++k) {
+          P[k][0] = P[0][0] + 0.5 * (P[k][0] - P[0][0]);
+          P[k][1] = P[0][1] + 0.5 * (P[k][1] - P[0][1]);
+          st = eval(alpha_of(P[k][0]), std::exp(P[k][1]), &F[k]);
+          if (st != SCF_OK) return st;
+        }
+      }
+    }
+  }
+  int kb = 0;
+  for (int k = 1; k < 3; ++k)
+    if (F[k] > F[kb]) kb = k;
+  ab[0] = alpha_of(P[kb][0]);
+  ab[1] = std::exp(P[kb][1]);
+  if (best_val) *best_val = F[kb];
+  return SCF_OK;
+}
+
+// new (alpha, b) for a plan, after the device has finished queued work
+scf_status set_basis_impl(scf_plan* p, double alpha, double b) {
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(SCF_ERR_UNSUPPORTED, "alpha = %g outside (0, 1]", alpha);
+  if (!(b > 0.0) || !std::isfinite(b)) return fail(SCF_ERR_INVALID_ARG, "b must be > 0");
+  HIP_TRY(hipDeviceSynchronize());
+  scf_basis nb = p->basis;
+  nb.alpha = alpha;
+  nb.b = b;
+  HIP_TRY(fill_tables(p, &nb));
+  return SCF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2127,7 +2257,8 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
   if (!(cfg->eta > 0.0) || !(cfg->dt_max > 0.0) || !(cfg->frac > 0.0 && cfg->frac <= 1.0) ||
       cfg->refresh_every < 1 || cfg->n_samples_tdyn < 0 || cfg->ns_max < 1 ||
       cfg->ns_max > SCF_MAX_SAMPLES || (cfg->n_samples_tdyn > 0 && !(cfg->c_dyn > 0.0)) ||
-      (cfg->recentre != 0 && cfg->recentre != 1))
+      (cfg->recentre != 0 && cfg->recentre != 1) || (cfg->retune != 0 && cfg->retune != 1) ||
+      (cfg->retune && !(cfg->alpha_min > 0.0 && cfg->alpha_min < 1.0)))
     return fail(SCF_ERR_INVALID_ARG, "invalid cadence parameters");
   if (!host || host->ncomp < 1)
     return fail(SCF_ERR_INVALID_ARG, "the cadence needs a host potential (its tidal tensor sets the interval)");
@@ -2210,6 +2341,14 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
             HIP_TRY(launch_shift3(p->dtype, n, (void*)sx[j], (void*)sy[j], (void*)sz[j], dx, s));
           for (int k = 0; k < 3; ++k) R[k] += dx[k];
         }
+        if (cfg->retune) {
+          // basis parameters of the zeroth mode closest to the selected particles
+          double ab[2] = {p->basis.alpha, p->basis.b};
+          st = tune_impl(p, n, x, y, z, wnew, cfg->alpha_min, ab, nullptr, wsp, C, s);
+          if (st != SCF_OK) return st;
+          st = set_basis_impl(p, ab[0], ab[1]);
+          if (st != SCF_OK) return st;
+        }
         st = complete_impl<Rt>(p, n, ns, sx, sy, sz, wnew, coef, wsp, C, s);
         if (st != SCF_OK) return st;
         if (cfg->recentre) {
@@ -2253,6 +2392,8 @@ scf_status scf_evolve(scf_plan* p, int64_t n, void* x, void* y, void* z, void* v
           e.dx[k] = dx[k];
           e.dv[k] = dv[k];
         }
+        e.alpha = p->basis.alpha;
+        e.b = p->basis.b;
       }
     }
     return SCF_OK;
@@ -2311,6 +2452,35 @@ scf_status scf_recentre(scf_plan* p, int64_t n, const void* x, const void* y, co
   const CadLayout C = cad_layout(p, n, 1);
   return recentre_impl(p, n, x, y, z, w, centre, tol, maxit, steps, (char*)ws, C,
                        (hipStream_t)stream);
+}
+
+
+scf_status scf_plan_set_basis(scf_plan* p, double alpha, double b) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  return set_basis_impl(p, alpha, b);
+}
+
+scf_status scf_plan_get_basis(const scf_plan* p, scf_basis* out) {
+  if (!p || !out) return fail(SCF_ERR_INVALID_ARG, "plan and out must be non-null");
+  *out = p->basis;
+  return SCF_OK;
+}
+
+scf_status scf_tune_basis(scf_plan* p, int64_t n, const void* x, const void* y, const void* z,
+                          const void* w, double alpha_min, double* alpha_b, double* a000,
+                          void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !alpha_b) return fail(SCF_ERR_INVALID_ARG, "plan and alpha_b must be non-null");
+  if (n < 0) return fail(SCF_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+  if (!(alpha_min > 0.0 && alpha_min < 1.0))
+    return fail(SCF_ERR_INVALID_ARG, "alpha_min must lie in (0, 1)");
+  if (!(alpha_b[1] > 0.0) || !std::isfinite(alpha_b[1]))
+    return fail(SCF_ERR_INVALID_ARG, "the starting b must be > 0");
+  if (n > 0 && !(ptr_ok(x) && ptr_ok(y) && ptr_ok(z) && ptr_ok(w)))
+    return fail(SCF_ERR_INVALID_ARG, "particle arrays must be non-null");
+  scf_status cs = check_cadence_ws(p, n, 1, ws, ws_bytes);
+  if (cs != SCF_OK) return cs;
+  const CadLayout C = cad_layout(p, n, 1);
+  return tune_impl(p, n, x, y, z, w, alpha_min, alpha_b, a000, (char*)ws, C, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -226,6 +226,10 @@ hipError_t launch_core_moments(int dtype, int64_t n, const void* x, const void* 
 hipError_t launch_recentre_sums(int dtype, int64_t n, const void* x, const void* y, const void* z,
                                 const void* w, const double* c, double binv, double alpha,
                                 int amode, double rmin, double* part, double* res, hipStream_t s);
+// sum over w > 0 of w (1 + (|x|/b)^(1/alpha))^(-alpha) into res[0] (double)
+hipError_t launch_a000_sum(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                           const void* w, double alpha, double binv, double* part, double* res,
+                           hipStream_t s);
 // a_k -= d[k] on three arrays of n
 hipError_t launch_shift3(int dtype, int64_t n, void* a0, void* a1, void* a2, const double* d,
                          hipStream_t s);

@@ -415,6 +415,40 @@ __global__ void __launch_bounds__(256) recentre_sums_kernel(int64_t n, const R* 
   if (threadIdx.x < 4) out[(int64_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Block sums (fixed order) of w (1 + (r/b)^(1/alpha))^(-alpha), r = |x|, over
+// the particles with w > 0, in double precision: the zeroth mode's projection
+// for the basis (alpha, b) up to its norm (out[blk][4], slot 0).
+template <typename R>
+__global__ void __launch_bounds__(256) a000_sum_kernel(int64_t n, const R* __restrict__ x,
+                                                       const R* __restrict__ y,
+                                                       const R* __restrict__ z,
+                                                       const R* __restrict__ w, double alpha,
+                                                       double binv, double* __restrict__ out) {
+#pragma clang fp contract(off)
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double q = 0.0;
+  if (i < n && w[i] > R(0)) {
+    const double xi = x[i], yi = y[i], zi = z[i];
+    const double s = sqrt((xi * xi + yi * yi) + zi * zi) * binv;
+    double f;
+    if (alpha == 1.0)
+      f = 1.0 / (1.0 + s);
+    else if (alpha == 0.5)
+      f = 1.0 / sqrt(1.0 + s * s);
+    else
+      f = pow(1.0 + pow(s, 1.0 / alpha), -alpha);
+    q = (double)w[i] * f;
+  }
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[(int64_t)blockIdx.x * 4 + threadIdx.x] = threadIdx.x == 0 ? red[0] : 0.0;
+}
+
 // a -= d for three arrays (a frame shift of positions or velocities)
 template <typename R>
 __global__ void __launch_bounds__(256) shift3_kernel(int64_t n, R* __restrict__ a0, R* __restrict__ a1,
@@ -580,6 +614,24 @@ hipError_t launch_shift3(int dtype, int64_t n, void* a0, void* a1, void* a2, con
   else
     shift3_kernel<double><<<blocks_of(n), 256, 0, s>>>(n, (double*)a0, (double*)a1, (double*)a2,
                                                        d[0], d[1], d[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_a000_sum(int dtype, int64_t n, const void* x, const void* y, const void* z,
+                           const void* w, double alpha, double binv, double* part, double* res,
+                           hipStream_t s) {
+  const int64_t nblk = n > 0 ? (int64_t)blocks_of(n) : 0;
+  if (n > 0) {
+    if (dtype == 0)
+      a000_sum_kernel<float><<<blocks_of(n), 256, 0, s>>>(n, (const float*)x, (const float*)y,
+                                                          (const float*)z, (const float*)w, alpha,
+                                                          binv, part);
+    else
+      a000_sum_kernel<double><<<blocks_of(n), 256, 0, s>>>(n, (const double*)x, (const double*)y,
+                                                           (const double*)z, (const double*)w,
+                                                           alpha, binv, part);
+  }
+  moments_sum_kernel<<<1, 256, 0, s>>>(part, nblk, res);
   return hipGetLastError();
 }
 

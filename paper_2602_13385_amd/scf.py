@@ -57,7 +57,8 @@ class CHost(C.Structure):
 class CCadence(C.Structure):
     _fields_ = [("eta", C.c_double), ("dt_max", C.c_double), ("frac", C.c_double),
                 ("c_dyn", C.c_double), ("refresh_every", C.c_int32), ("n_samples_tdyn", C.c_int32),
-                ("ns_max", C.c_int32), ("recentre", C.c_int32)]
+                ("ns_max", C.c_int32), ("recentre", C.c_int32), ("retune", C.c_int32),
+                ("pad", C.c_int32), ("alpha_min", C.c_double)]
 
 
 class CCadenceState(C.Structure):
@@ -69,7 +70,8 @@ class CIntervalLog(C.Structure):
     _fields_ = [("dt_int", C.c_double), ("nsub", C.c_int32), ("nsamples", C.c_int32),
                 ("complete", C.c_int32), ("pad", C.c_int32), ("nbound", C.c_int64),
                 ("nchanged", C.c_int64), ("rx", C.c_double), ("rhm", C.c_double),
-                ("mbound", C.c_double), ("dx", C.c_double * 3), ("dv", C.c_double * 3)]
+                ("mbound", C.c_double), ("dx", C.c_double * 3), ("dv", C.c_double * 3),
+                ("alpha", C.c_double), ("b", C.c_double)]
 
 
 MAX_SAMPLES = 16
@@ -89,11 +91,14 @@ class Cadence:
     c_dyn: float = C_DYN
     ns_max: int = 8
     recentre: bool = False
+    retune: bool = False
+    alpha_min: float = 0.25
 
     def c(self):
         return CCadence(float(self.eta), float(self.dt_max), float(self.frac), float(self.c_dyn),
                         int(self.refresh_every), int(self.n_samples_tdyn), int(self.ns_max),
-                        1 if self.recentre else 0)
+                        1 if self.recentre else 0, 1 if self.retune else 0, 0,
+                        float(self.alpha_min))
 
 
 def _state_dict(st):
@@ -155,6 +160,10 @@ SIGNATURES = {
                            C.c_size_t, _vp]),
     "scf_recentre": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _dp, C.c_double, C.c_int32,
                                C.POINTER(C.c_int32), _vp, C.c_size_t, _vp]),
+    "scf_tune_basis": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, C.c_double, _dp, _dp, _vp,
+                                 C.c_size_t, _vp]),
+    "scf_plan_set_basis": (C.c_int, [_vp, C.c_double, C.c_double]),
+    "scf_plan_get_basis": (C.c_int, [_vp, C.POINTER(CBasis)]),
     "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
     "scf_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -540,8 +549,9 @@ class Plan:
         log = [{"dt_int": e.dt_int, "nsub": e.nsub, "nsamples": e.nsamples,
                 "kind": "complete" if e.complete else "intermediate", "nbound": e.nbound,
                 "nchanged": e.nchanged, "rx": e.rx, "rhm": e.rhm, "mbound": e.mbound,
-                "dx": np.array(e.dx[:]), "dv": np.array(e.dv[:])}
+                "dx": np.array(e.dx[:]), "dv": np.array(e.dv[:]), "alpha": e.alpha, "b": e.b}
                for e in logs[:int(nint)]]
+        self._sync_basis()
         return np.array(cen[:]), _state_dict(cs), log
 
     def density(self, x, y, z, coef):
@@ -578,3 +588,27 @@ class Plan:
                                   float(tol), int(maxit), C.byref(steps), _ptr(ws), ws.numel(),
                                   _stream()))
         return np.array(c[:]), int(steps.value)
+
+    def _sync_basis(self):
+        b = CBasis()
+        _check(lib().scf_plan_get_basis(self._h, C.byref(b)))
+        self.basis = b
+        self.alpha, self.b = float(b.alpha), float(b.b)
+
+    def set_basis(self, alpha, b):
+        """Replace the plan's alpha and b (tables recomputed)."""
+        _check(lib().scf_plan_set_basis(self._h, float(alpha), float(b)))
+        self._sync_basis()
+
+    def tune_basis(self, x, y, z, w, alpha_min=0.25, start=None):
+        """(alpha, b) maximising a_000 of the particles with w > 0 about the
+        origin, and that maximum; the plan is not changed."""
+        self._check_arrays(x, y, z, w)
+        n = x.numel()
+        ab = (C.c_double * 2)(*(start if start is not None else (self.alpha, self.b)))
+        val = C.c_double()
+        ws = self.cadence_workspace(n, 1, device=x.device)
+        _check(lib().scf_tune_basis(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(w),
+                                    float(alpha_min), C.cast(ab, _dp), C.byref(val), _ptr(ws),
+                                    ws.numel(), _stream()))
+        return float(ab[0]), float(ab[1]), float(val.value)

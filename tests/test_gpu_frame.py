@@ -93,3 +93,74 @@ def test_evolve_with_recentre_matches_oracle(torch, S, O):
         assert np.abs(out[rows] - st_ref[rows]).max() <= 1e-11 * np.abs(st_ref[rows]).max()
     assert np.abs(cen - cen_ref).max() <= 1e-11 * np.abs(cen_ref).max()
     assert np.abs(coef.cpu().numpy() - coef_ref).max() <= 1e-11 * np.abs(coef_ref).max()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("profile", ["hernquist", "plummer"])
+def test_tune_basis_matches_oracle(torch, S, O, dtype, profile):
+    """The a_000 maximum over (alpha, b) against the oracle's independent
+    optimiser; both converge to about 1e-7, so they agree to 2e-6."""
+    print(f"[frame] tune {dtype} {profile}", flush=True)
+    p = I.hernquist(20000, 85) if profile == "hernquist" else I.plummer(20000, 85)
+    pos = _rounded(p.pos * 1.7, dtype)
+    w = _rounded(p.mass, dtype)
+    a_ref, b_ref, v_ref = F.tune_basis(pos, w, alpha0=1.0, b0=1.0)
+    plan = S.Plan(6, 2, dtype=dtype)
+    a, b, v = plan.tune_basis(*[_dev(torch, pos[i], dtype) for i in range(3)], _dev(torch, w, dtype))
+    assert abs(a - a_ref) <= 2e-6 and abs(b / b_ref - 1.0) <= 2e-6, (a, a_ref, b, b_ref)
+    assert v >= v_ref - 1e-12 * abs(v_ref)
+    assert plan.alpha == 1.0 and plan.b == 1.0  # the plan itself is unchanged
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_set_basis_equals_a_new_plan(torch, S, dtype):
+    p = I.plummer(8000, 86)
+    st = [_dev(torch, p.state()[i], dtype) for i in range(6)]
+    m = _dev(torch, p.mass, dtype)
+    plan = S.Plan(10, 6, dtype=dtype)
+    plan.coeffs(st[0], st[1], st[2], m)
+    plan.set_basis(0.7, 1.3)
+    assert plan.alpha == 0.7 and plan.b == 1.3
+    ref = S.Plan(10, 6, alpha=0.7, b=1.3, dtype=dtype)
+    c1 = plan.coeffs(st[0], st[1], st[2], m)
+    c2 = ref.coeffs(st[0], st[1], st[2], m)
+    assert torch.equal(c1, c2)
+    a1 = plan.forces(st[0], st[1], st[2], c1)
+    a2 = ref.forces(st[0], st[1], st[2], c2)
+    assert all(torch.equal(u, v) for u, v in zip(a1, a2))
+
+
+def test_evolve_with_retune_matches_oracle(torch, S, O):
+    """Plummer (N = 2000) in the logarithmic host, starting from the
+    alpha = 1, b = 1 basis, with recentring and retuning at every 2nd
+    interval (FP64).  The optimisers agree to about 1e-7 in (alpha, b), so
+    the runs are compared at 1e-5."""
+    p = I.plummer(2000, 87)
+    st0 = p.state()
+    st0[:3] += np.array([[0.1], [0.0], [-0.05]])
+    m = p.mass
+    B = O.basis(10, 6)
+    H = O.host([(O.HOST_LOG, (1.5, 1.0, 0.0))])
+    cen0 = np.array([20.0, 0.0, 0.0, 0.0, I.LOG_VC_20, 0.0])
+    coef0, w0, i0 = K.initial_refresh(B, st0, m, 0.999)
+    st_ref, cen_ref, coef_ref, w_ref, cs_ref, log_ref, B_ref = K.evolve(
+        B, H, st0, m, cen0, coef0, w0, 4, eta=1.0 / 400.0, dt_max=0.05, refresh_every=2,
+        mbound=i0["mbound"], rhm=i0["rhm"], recentre=True, retune=True)
+    assert abs(B_ref.alpha - 1.0) > 1e-2  # the basis really moved
+    plan = S.Plan(10, 6, dtype="f64")
+    st = [_dev(torch, st0[i], "f64") for i in range(6)]
+    md = _dev(torch, m, "f64")
+    coef, w, state = plan.cadence_init(st, md, 0.999)
+    cad = S.Cadence(eta=1.0 / 400.0, dt_max=0.05, frac=0.999, refresh_every=2, recentre=True,
+                    retune=True)
+    cen, state, log = plan.evolve(st, md, 4, cad, (LOG_HOST, 1.0), cen0, coef, w, state)
+    torch.cuda.synchronize()
+    for g, r in zip(log, log_ref):
+        for k in ("nsub", "kind", "nbound", "nchanged"):
+            assert g[k] == r[k], (k, g, r)
+        assert abs(g["alpha"] - r["alpha"]) <= 2e-6 and abs(g["b"] / r["b"] - 1.0) <= 2e-6
+    assert abs(plan.alpha - B_ref.alpha) <= 2e-6
+    out = np.stack([t.cpu().numpy() for t in st])
+    for rows in (slice(0, 3), slice(3, 6)):
+        assert np.abs(out[rows] - st_ref[rows]).max() <= 1e-5 * np.abs(st_ref[rows]).max()
+    assert np.abs(coef.cpu().numpy() - coef_ref).max() <= 1e-5 * np.abs(coef_ref).max()

@@ -7,6 +7,11 @@
   shift, by symmetry.
 * alpha = 1 (a cusp at every particle): the result is a local maximum of
   a_000 at the scale of 1e-3, and the iteration never lowers a_000.
+* The basis parameters: the closed-form energy norm of the zeroth mode equals
+  the oracle's quadrature of it; the potential of a Hernquist sphere is the
+  alpha = 1 zeroth mode and that of a Plummer sphere the alpha = 1/2 one, so
+  a_000 is largest there (b = their scale radius); scaling the positions
+  scales b.
 """
 import numpy as np
 import pytest
@@ -53,3 +58,21 @@ def test_cusped_kernel_local_maximum_and_ascent(O):
     g0 = F.a000_about(B, pos, w, c)
     for e in np.vstack([np.eye(3), -np.eye(3)]):
         assert F.a000_about(B, pos, w, c + 1e-3 * e) <= g0
+
+
+@pytest.mark.parametrize("alpha,b,G", [(1.0, 1.0, 1.0), (0.5, 1.0, 1.0), (0.8, 1.7, 0.6)])
+def test_zeroth_mode_norm_closed_form(O, alpha, b, G):
+    B = O.basis(1, 0, alpha=alpha, b=b, G=G)
+    assert F.n00(alpha, b, G) == pytest.approx(O.norms(B)[0], rel=1e-10)
+    q = I.quadrature_sphere("hernquist", 1.0, nr=24, nmu=8, nphi=8)
+    assert F.a000_basis(q.pos, q.mass, alpha, b, G) == pytest.approx(
+        O.coeffs(B, *q.pos, q.mass)[0], rel=1e-12)
+
+
+@pytest.mark.parametrize("profile,alpha_true", [("hernquist", 1.0), ("plummer", 0.5)])
+def test_tuned_basis_of_exact_profiles(O, profile, alpha_true):
+    q = I.quadrature_sphere(profile, alpha_true, nr=40, nmu=8, nphi=8, a=1.0)
+    for scale in (1.0, 2.5):
+        a, b, _ = F.tune_basis(q.pos * scale, q.mass, alpha0=0.7, b0=0.8)
+        assert a == pytest.approx(alpha_true, abs=1e-6)
+        assert b == pytest.approx(scale, rel=1e-6)
