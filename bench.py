@@ -445,7 +445,9 @@ def device_info(torch):
         except OSError:
             continue
         active = [ln for ln in levels if ln.endswith("*")]
-        info["sclk"] = active[0] if active else (levels[-1] if levels else None)
+        # the level the driver reports at the moment of the read (the clock
+        # drops within milliseconds of the GPU going idle)
+        info["sclk_level_at_read"] = active[0] if active else (levels[-1] if levels else None)
         break
     return info
 
