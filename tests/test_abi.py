@@ -82,3 +82,33 @@ def test_tidal_norm_matches_oracle(S, O):
     for pos in ([20.0, 0.0, 0.0], [3.0, -4.0, 0.5], [0.2, 0.1, -8.0]):
         ref = O.tidal_norm(H, pos)
         assert S.tidal_norm((comps, 1.0), pos) == pytest.approx(ref, rel=1e-13)
+
+
+def test_cadence_density_frame_calls_reject_a_null_plan(S):
+    """The refresh-cadence, density and frame entry points validate their
+    arguments before any device work."""
+    L = S.lib()
+    st = S.CCadenceState()
+    cad = S.Cadence().c()
+    out = (C.c_double * 5)()
+    ab = (C.c_double * 2)(1.0, 1.0)
+    sz = C.c_size_t()
+    assert L.scf_cadence_workspace_size(None, 10, 1, C.byref(sz)) == 1
+    assert L.scf_step_frozen(None, 10, *[None] * 9, 0, None, None, None, 0.01, 1, None, 0, None) == 1
+    assert L.scf_select(None, 10, *[None] * 8, 0.999, None, None, C.byref(st), None, 0, None) == 1
+    assert L.scf_coeffs_delta(None, 10, 1, None, None, None, None, None, None, 0, None) == 1
+    assert L.scf_cadence_init(None, 10, *[None] * 7, 0.999, None, None, C.byref(st), None, 0,
+                              None) == 1
+    assert L.scf_evolve(None, 10, *[None] * 10, None, None, C.byref(cad), 1, None, None,
+                        C.byref(st), None, None, 0, None) == 1
+    assert L.scf_density(None, 10, None, None, None, None, None, None, 0, None) == 1
+    assert L.scf_core(None, 10, *[None] * 9, C.cast(out, C.POINTER(C.c_double)), None, 0,
+                      None) == 1
+    assert L.scf_recentre(None, 10, None, None, None, None, C.cast(out, C.POINTER(C.c_double)),
+                          1e-6, 10, None, None, 0, None) == 1
+    assert L.scf_tune_basis(None, 10, None, None, None, None, 0.25,
+                            C.cast(ab, C.POINTER(C.c_double)), None, None, 0, None) == 1
+    assert L.scf_plan_set_basis(None, 0.5, 1.0) == 1
+    assert L.scf_plan_get_basis(None, None) == 1
+    for name in ("scf_select", "scf_evolve", "scf_tune_basis"):
+        assert len(L.scf_last_error()) > 0, name

@@ -207,3 +207,44 @@ def test_evolve_matches_oracle(torch, S, O, dtype, nint, every, dt_max, nsamp):
         assert _rel(out[rows], st_ref[rows]) <= TOL[dtype] * (10 if dtype == "f32" else 1)
     assert np.abs(cen - cen_ref).max() <= 1e-12 * np.abs(cen_ref).max()
     assert _rel(coef.cpu().numpy(), coef_ref) <= TOL[dtype] * (10 if dtype == "f32" else 1)
+
+
+def test_cadence_rejects_bad_parameters(torch, S):
+    st0, m = _cluster(500, 91, 1.0, "f32")
+    plan = S.Plan(10, 6, dtype="f32")
+    st = [_dev(torch, st0[i], "f32") for i in range(6)]
+    md = _dev(torch, m, "f32")
+    coef, w, state = plan.cadence_init(st, md, 0.999)
+    cen0 = np.array([20.0, 0.0, 0.0, 0.0, I.LOG_VC_20, 0.0])
+    for bad in (dict(eta=0.0), dict(dt_max=-1.0), dict(frac=1.5), dict(frac=0.0),
+                dict(refresh_every=0), dict(ns_max=0), dict(ns_max=17),
+                dict(n_samples_tdyn=1, c_dyn=0.0), dict(retune=True, alpha_min=1.0)):
+        with pytest.raises(S.ScfError) as e:
+            plan.evolve(st, md, 1, S.Cadence(**bad), (LOG_HOST, 1.0), cen0, coef, w, state)
+        assert e.value.status == 1, bad
+    with pytest.raises(S.ScfError):  # the interval comes from a host tidal tensor
+        plan.evolve(st, md, 1, S.Cadence(), ([], 1.0), cen0, coef, w, state)
+    with pytest.raises(S.ScfError):
+        plan.select(st, md, coef, frac=1.5)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_cadence_density_frame_calls_on_no_particles(torch, S, dtype):
+    plan = S.Plan(10, 6, dtype=dtype)
+    td = torch.float32 if dtype == "f32" else torch.float64
+    st = [torch.empty(0, dtype=td, device="cuda") for _ in range(6)]
+    m = torch.empty(0, dtype=td, device="cuda")
+    coef, w, state = plan.cadence_init(st, m, 0.999)
+    torch.cuda.synchronize()
+    assert state["nbound"] == 0 and float(coef.abs().max()) == 0.0
+    cen0 = np.array([20.0, 0.0, 0.0, 0.0, I.LOG_VC_20, 0.0])
+    cen, state, log = plan.evolve(st, m, 2, S.Cadence(dt_max=0.1, refresh_every=1, recentre=True),
+                                  (LOG_HOST, 1.0), cen0, coef, w, state)
+    assert [e["nbound"] for e in log] == [0, 0]
+    assert np.all(np.isfinite(cen))
+    assert plan.density(st[0], st[1], st[2], coef).numel() == 0
+    assert plan.core(st, m, m, coef)[2] == 0.0
+    c, _ = plan.recentre(st[0], st[1], st[2], m, centre=(0.5, 0.0, 0.0))
+    assert np.array_equal(c, [0.5, 0.0, 0.0])
+    _, nch = plan.select(st, m, coef)[0], plan.coeffs_delta([st[:3]], m, m, coef)
+    assert nch == 0
