@@ -388,9 +388,12 @@ scf_status scf_plan_set_basis(scf_plan* plan, double alpha, double b);
 scf_status scf_plan_get_basis(const scf_plan* plan, scf_basis* out);
 
 /* Launch configuration.  The coefficient kernel has several compiled
- * variants (lanes per particle in the basis phase, waves per block).
- * scf_autotune times each on the given particles (synchronising the stream)
- * and keeps the fastest for the plan; best_ms (nullable) receives its time.
+ * variants (lanes per particle in the basis phase, waves per block), and its
+ * grid is one resident round of wave-units divided by 1, 2, 4 or 8 (fewer,
+ * longer units amortise their set-up and partial row when n is small).
+ * scf_autotune times each (variant, divisor) on the given particles
+ * (synchronising the stream) and keeps the fastest for the plan; best_ms
+ * (nullable) receives its time.
  * Variants give results that agree to rounding (the particle sums are grouped
  * differently); a fixed variant is bitwise reproducible. */
 int32_t scf_plan_num_variants(const scf_plan* plan);
@@ -398,6 +401,8 @@ int32_t scf_plan_num_variants(const scf_plan* plan);
 int32_t scf_plan_graph_captures(const scf_plan* plan);
 int32_t scf_plan_variant(const scf_plan* plan);
 scf_status scf_plan_set_variant(scf_plan* plan, int32_t variant);
+int32_t scf_plan_coef_units_div(const scf_plan* plan);
+scf_status scf_plan_set_coef_units_div(scf_plan* plan, int32_t div);
 const char* scf_plan_describe(const scf_plan* plan);
 scf_status scf_autotune(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
                         const void* m, void* ws, size_t ws_bytes, void* stream, double* best_ms);

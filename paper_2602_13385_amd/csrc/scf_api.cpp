@@ -176,6 +176,7 @@ struct scf_plan {
   int amode;
   Engine* eng;
   int coef_variant = 0;
+  int coef_div = 1;  // wave-units of the coefficient pass: one resident round / coef_div
   int field_variant = 0;
   int num_cu = 256;
   int resident[8] = {1, 1, 1, 1, 1, 1, 1, 1};  // resident wave-units per CU per variant
@@ -244,19 +245,21 @@ struct Timed {
 // Coefficient launch geometry: one resident round of wave-units (the
 // occupancy of the variant times the CU count), each taking an even share of
 // the P-particle stages; returns the unit count and sets *stages.
-int coef_units_v(const scf_plan* p, int64_t n, int v, int64_t* stages) {
+int coef_units_v(const scf_plan* p, int64_t n, int v, int64_t* stages, int div = 1) {
   if (n <= 0) {
     *stages = 0;
     return 0;
   }
   const int P = p->eng->stage_particles(v);
   *stages = (n + P - 1) / P;
-  const int64_t cap = (int64_t)p->resident[v] * p->num_cu;
+  const int64_t cap = (int64_t)p->resident[v] * p->num_cu / std::max(div, 1);
   return (int)std::min<int64_t>(*stages, std::max<int64_t>(cap, 1));
 }
 
+// the plan's variant, and its unit count (fewer, longer units suit small n:
+// the per-unit set-up and partial row are amortised over more stages)
 int coef_units(const scf_plan* p, int64_t n, int64_t* stages) {
-  return coef_units_v(p, n, p->coef_variant, stages);
+  return coef_units_v(p, n, p->coef_variant, stages, p->coef_div);
 }
 
 // partial-sum rows of the current variant
@@ -712,6 +715,16 @@ int32_t scf_plan_num_variants(const scf_plan* p) { return p ? p->eng->coef_varia
 
 int32_t scf_plan_variant(const scf_plan* p) { return p ? p->coef_variant : -1; }
 
+int32_t scf_plan_coef_units_div(const scf_plan* p) { return p ? p->coef_div : -1; }
+
+scf_status scf_plan_set_coef_units_div(scf_plan* p, int32_t div) {
+  if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
+  if (div != 1 && div != 2 && div != 4 && div != 8)
+    return fail(SCF_ERR_INVALID_ARG, "div = %d is not 1, 2, 4 or 8", div);
+  p->coef_div = div;
+  return SCF_OK;
+}
+
 scf_status scf_plan_set_variant(scf_plan* p, int32_t v) {
   if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
   if (v < 0 || v >= p->eng->coef_variants())
@@ -739,16 +752,20 @@ scf_status scf_autotune(scf_plan* p, int64_t n, const void* x, const void* y, co
   const int saved = p->coef_variant;
   const bool prof = p->prof;
   p->prof = false;
-  int best = saved;
+  const int saved_div = p->coef_div;
+  int best = saved, best_div = saved_div;
   float bms = 1e30f;
-  for (int v = 0; v < p->eng->coef_variants(); ++v) {
+  for (int cand = 0; cand < 4 * p->eng->coef_variants(); ++cand) {
+    const int v = cand / 4, div = 1 << (cand % 4);
     p->coef_variant = v;
+    p->coef_div = div;
     float tot = 0.f;
     for (int rep = 0; rep < 4; ++rep) {
       HIP_TRY(hipEventRecord(e0, s));
       scf_status st = scf_coeffs(p, n, x, y, z, m, coef, ws, ws_bytes, stream);
       if (st != SCF_OK) {
         p->coef_variant = saved;
+        p->coef_div = saved_div;
         p->prof = prof;
         return st;
       }
@@ -761,11 +778,13 @@ scf_status scf_autotune(scf_plan* p, int64_t n, const void* x, const void* y, co
     if (tot < bms) {
       bms = tot;
       best = v;
+      best_div = div;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   p->coef_variant = best;
+  p->coef_div = best_div;
   p->prof = prof;
   if (best_ms) *best_ms = bms / 3.0;
   return SCF_OK;

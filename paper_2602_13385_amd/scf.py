@@ -132,6 +132,8 @@ SIGNATURES = {
     "scf_plan_variant": (C.c_int32, [_vp]),
     "scf_plan_graph_captures": (C.c_int32, [_vp]),
     "scf_plan_set_variant": (C.c_int, [_vp, C.c_int32]),
+    "scf_plan_coef_units_div": (C.c_int32, [_vp]),
+    "scf_plan_set_coef_units_div": (C.c_int, [_vp, C.c_int32]),
     "scf_plan_describe": (C.c_char_p, [_vp]),
     "scf_autotune": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp, _dp]),
     "scf_plan_num_field_variants": (C.c_int32, [_vp]),
@@ -274,6 +276,14 @@ class Plan:
 
     def describe(self):
         return lib().scf_plan_describe(self._h).decode()
+
+    @property
+    def coef_units_div(self):
+        return int(lib().scf_plan_coef_units_div(self._h))
+
+    @coef_units_div.setter
+    def coef_units_div(self, d):
+        _check(lib().scf_plan_set_coef_units_div(self._h, int(d)))
 
     @property
     def field_variant(self):
