@@ -109,7 +109,8 @@ def run_main(dtype, steps, warmup, torch, scf, I, profile):
         plan.profile(False)
     return {"n": n, "T": plan.T, "nmax": w.nmax, "lmax": w.lmax, "ms": ms, "wall_s": wall,
             "kernels": kt, "dt": w.dt, "name": w.name, "variant": variant,
-            "field_variant": plan.field_variant, "plan": plan, "describe": plan.describe()}
+            "field_variant": plan.field_variant, "coef_units_div": plan.coef_units_div,
+            "plan": plan, "describe": plan.describe()}
 
 
 def accuracy_main(torch, scf, I):
@@ -558,7 +559,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": r["name"], "N": n, "nmax": r["nmax"], "lmax": r["lmax"], "T": T,
                    "alpha": 1.0, "dt": r["dt"], "host": None, "coef_variant": r["variant"],
-                   "field_variant": r["field_variant"]},
+                   "field_variant": r["field_variant"], "coef_units_div": r["coef_units_div"]},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic(dom), "flops_per_launch": fl[dom] * n,

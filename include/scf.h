@@ -407,13 +407,19 @@ const char* scf_plan_describe(const scf_plan* plan);
 scf_status scf_autotune(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
                         const void* m, void* ws, size_t ws_bytes, void* stream, double* best_ms);
 
-/* The field kernel has compiled variants too (register budget per thread:
- * the compiler's own, or one that allows at least 4 waves per SIMD).
- * scf_autotune_field computes the coefficients of the given particles, times
- * each variant on the forces at those particles (written to ax, ay, az,
- * device, caller-owned; synchronising the stream) and keeps the fastest for
- * the plan; best_ms (nullable) receives its time.  The variants give bitwise
- * identical results. */
+/* The field kernel has compiled variants too.  Variants 0 and 1 evaluate the
+ * radial sums of Eq. total_potential on the vector ALUs, under two register
+ * budgets per thread (the compiler's own, or one that allows at least 4 waves
+ * per SIMD); their results are bitwise identical.  Single-precision plans add
+ * variants 2 and 3: the same sums as 4x4x1 matrix-core (MFMA) products in
+ * persistent blocks, again under two register budgets (the compiler's own, or
+ * 5 waves per SIMD); these two agree bitwise with each other and, since they
+ * sum in another order, with variants 0 and 1 to the single-precision force
+ * tolerance.  The batched and adjoint passes run variant 1's kernel whenever
+ * a variant >= 1 is set.  scf_autotune_field computes the coefficients of
+ * the given particles, times each variant on the forces at those particles
+ * (written to ax, ay, az, device, caller-owned; synchronising the stream) and
+ * keeps the fastest for the plan; best_ms (nullable) receives its time. */
 int32_t scf_plan_num_field_variants(const scf_plan* plan);
 int32_t scf_plan_field_variant(const scf_plan* plan);
 scf_status scf_plan_set_field_variant(scf_plan* plan, int32_t variant);

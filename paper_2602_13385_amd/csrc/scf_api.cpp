@@ -300,6 +300,7 @@ void scf_plan_destroy(scf_plan* p) {
   if (p->d_beta_rad) (void)hipFree(p->d_beta_rad);
   if (p->d_beta_ang) (void)hipFree(p->d_beta_ang);
   if (p->d_kden) (void)hipFree(p->d_kden);
+  if (p->d_dtab) (void)hipFree(p->d_dtab);
   if (p->d_cs) (void)hipFree(p->d_cs);
   if (p->d_fw) (void)hipFree(p->d_fw);
   delete p;

@@ -75,6 +75,9 @@ struct ForceArgs {
   const int64_t* blk_end;
   const double* centre_tab;    // [nclusters][9]: R, grad psi_host(R), unused
   int64_t W_stride;            // elements between clusters' W tables
+  // matrix-core field pass: per degree, 1 / kappa_n and 2 (n + lam) kappa_n
+  // (kappa_n the leading coefficient of C_n^lam), [l][2][NMAXC + 1]
+  const double* dtab;
 };
 
 // Kernel arguments of the adjoint's Hessian-vector kernel (T = float or double).

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <type_traits>
 
 #include "scf_device.h"
 #include "scf_internal.h"
@@ -509,6 +510,12 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
   }
 }
 
+template <typename R, int MODE>
+__device__ __forceinline__ void field_store(const ForceArgs<R>& a, const int64_t i, const R x,
+                                            const R y, const R z, const R psi, R axv, R ayv, R azv,
+                                            const R cx, const R cy, const R cz, const R gcx,
+                                            const R gcy, const R gcz);
+
 // Body of the field kernel: one particle per thread of a 256-thread block.
 template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
 __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
@@ -538,6 +545,16 @@ __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
   R psi, axv, ayv, azv;
   field_eval<R, NMAXC, LMAX>(x, y, z, W, a.beta_rad, a.beta_ang, a.binv, a.alpha, a.inv_alpha,
                              a.amode, psi, axv, ayv, azv);
+  field_store<R, MODE>(a, i, x, y, z, psi, axv, ayv, azv, cx, cy, cz, gcx, gcy, gcz);
+}
+
+// Host tidal field and the stores of one particle: the forces (mode 0), the
+// fused kick and drift (mode 1) or the adjoint accumulation (mode 2).
+template <typename R, int MODE>
+__device__ __forceinline__ void field_store(const ForceArgs<R>& a, const int64_t i, const R x,
+                                            const R y, const R z, const R psi, R axv, R ayv, R azv,
+                                            const R cx, const R cy, const R cz, const R gcx,
+                                            const R gcy, const R gcz) {
   if (a.host.ncomp > 0) {
     R hx, hy, hz;
     host_grad<R>(a.host, cx + x, cy + y, cz + z, hx, hy, hz);
@@ -593,6 +610,308 @@ template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 field_kernel_o4(ForceArgs<R> a) {
   field_body<R, NMAXC, LMAX, MODE, BATCHED>(a);
+}
+
+// ---------------------------------------------------------------------------
+// field pass on the matrix cores (single precision)
+// ---------------------------------------------------------------------------
+// For one (l, m) the field needs four radial sums over n: sigma_c = sum_n W^c_n
+// p_n, sigma_s likewise, and their xi-derivatives.  The derivative of the monic
+// Gegenbauer basis is again a combination of that basis, d p_n / d xi =
+// sum_k D_nk p_k, so the derivatives are sums over the same p_k with the
+// coefficients W'_k = sum_n D_nk W_n.  The four sums of a wave's 64 particles
+// are then one chain of 4x4x1 16-block FP32 MFMAs over n: the A operand is the
+// coefficient quadruple (W^c, W'^c, W^s, W'^s)_n broadcast from one block, the
+// B operand is each lane's own p_n, and row r of the product lands in result
+// register r of that lane.  The quadruples live in LDS in register layout: for
+// degree l, quadruple q = m NW + n is block q % 16 (lanes 4 (q % 16) + r) of
+// register q / 16, so a degree's operands are NV coalesced LDS reads per lane
+// and every MFMA names its block as an immediate.  The Legendre recurrence,
+// the radial recurrence and the angular combination stay on the VALU, where
+// they overlap with the matrix-core chains of the other waves.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// orders whose accumulation chains one wave interleaves
+constexpr int MFMA_GROUP = 2;
+
+template <int NMAXC, int LMAX>
+struct MfmaShape {
+  static constexpr int L1 = LMAX + 1, NW = NMAXC + 1;
+  // operand registers of degree l, and of the degrees below l
+  static constexpr int nv(int l) { return ((l + 1) * NW + 15) / 16; }
+  static constexpr int off(int l) {
+    int s = 0;
+    for (int k = 0; k < l; ++k) s += nv(k);
+    return s;
+  }
+  static constexpr int IMG = off(L1) * 64;  // floats of the LDS operand image
+  // radial recurrence constants b_n of each degree (rows of 4-float multiples)
+  static constexpr int TS = (NW + 3) / 4 * 4;
+  static constexpr int TAB = L1 * TS;
+};
+
+// Monic Legendre recurrence constant b_{l,m} (b_{m,m} = -1 starts order m).
+__host__ __device__ constexpr double legendre_b(int l, int m) {
+  return l == m ? -1.0
+                : (l < m + 2 ? 0.0
+                             : (l + m - 1.0) * (l - m - 1.0) / ((2.0 * l - 1.0) * (2.0 * l - 3.0)));
+}
+
+template <int Q>
+__device__ __forceinline__ mfma_f4 mfma_bcast(const float a, const float b, const mfma_f4 c) {
+  // CBSZ = 4: all 16 blocks take their A operand from block ABID = Q % 16
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, Q & 15, 0);
+}
+
+template <int I, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < E) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(f);
+  }
+}
+template <int I, int STEP, typename F>
+__device__ __forceinline__ void static_for_down(F&& f) {
+  if constexpr (I >= 0) {
+    f(std::integral_constant<int, I>{});
+    static_for_down<I - STEP, STEP>(f);
+  }
+}
+
+// The LDS operand image of a block and the radial recurrence constants.  The
+// image is zeroed first; then thread t < (LMAX + 1)^2 fills the quadruples of
+// row t = (l, j) of the force weights W (rows n > nmax of W are zero): W_n,
+// and the derivative coefficients W'_k = 2 (k + lam) kappa_k S_k from the
+// suffix sums S_k = W_{k+1} / kappa_{k+1} + S_{k+2}, formed in double
+// precision from the per-degree table dtab ([l][0][n] = 1 / kappa_n,
+// [l][1][n] = 2 (n + lam) kappa_n).
+template <int NMAXC, int LMAX>
+__device__ __forceinline__ void build_mfma_operands(float* img, float* tab,
+                                                    const float* __restrict__ W,
+                                                    const double* __restrict__ dtab,
+                                                    const float* __restrict__ bR) {
+  using S = MfmaShape<NMAXC, LMAX>;
+  constexpr int NW = S::NW;
+  static_assert(S::IMG % 4 == 0, "operand image in float4 units");
+  for (int e = threadIdx.x; e < S::IMG / 4; e += blockDim.x)
+    reinterpret_cast<float4*>(img)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int e = threadIdx.x; e < S::TAB; e += blockDim.x) {
+    const int l = e / S::TS, n = e - l * S::TS;
+    tab[e] = n < NW ? bR[l * NW + n] : 0.f;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  static_for<0, S::L1>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    if (t >= l * l && t < (l + 1) * (l + 1)) {
+      const int j = t - l * l;
+      const int m = (j + 1) >> 1;
+      // j = 0 and odd j: cosine part (rows 0, 1); even j > 0: sine part (rows 2, 3)
+      const int r0 = (j > 0 && (j & 1) == 0) ? 2 : 0;
+      const float* __restrict__ Wr = W + t * NW;
+      const double* __restrict__ ik = dtab + l * 2 * NW;
+      const double* __restrict__ dk = ik + NW;
+      float w[NW];
+#pragma unroll
+      for (int n = 0; n < NW; ++n) w[n] = Wr[n];
+      float* dst = img + S::off(l) * 64 + r0;
+      double s1 = 0.0, s2 = 0.0;  // S_{k+1}, S_{k+2}
+#pragma unroll
+      for (int k = NMAXC; k >= 0; --k) {
+        const double v = k < NMAXC ? (double)w[k < NMAXC ? k + 1 : 0] * ik[k < NMAXC ? k + 1 : 0]
+                                   : 0.0;
+        const double sk = v + s2;
+        s2 = s1;
+        s1 = sk;
+        const int q = m * NW + k;
+        float* d = dst + (q >> 4) * 64 + 4 * (q & 15);
+        d[0] = w[k];
+        d[1] = (float)(dk[k] * sk);
+      }
+    }
+  });
+}
+
+template <int NMAXC, int LMAX>
+__device__ __noinline__ void build_mfma_operands_call(float* img, float* tab,
+                                                      const float* __restrict__ W,
+                                                      const double* __restrict__ dtab,
+                                                      const float* __restrict__ bR) {
+  build_mfma_operands<NMAXC, LMAX>(img, tab, W, dtab, bR);
+}
+
+// psi_SCF and a = -grad psi_SCF at one point per lane; every lane of the wave
+// must be active (the MFMAs mix the lanes' operands).  Degrees and orders are
+// compile-time sweeps, so one point's whole evaluation is straight-line code
+// that the scheduler can interleave freely.
+template <int NMAXC, int LMAX>
+__device__ __forceinline__ void field_eval_mfma(const float x, const float y, const float z,
+                                                const float* img, const float* tab,
+                                                const float binv, const float alpha,
+                                                const float inv_alpha, const int amode,
+                                                float& psi, float& axv, float& ayv, float& azv) {
+  using S = MfmaShape<NMAXC, LMAX>;
+  constexpr int L1 = S::L1, NW = S::NW;
+  const int lane = threadIdx.x & 63;
+  Geom<float> g = make_geom<float>(x, y, z, binv, alpha, inv_alpha, amode);
+  float Er[L1], Ei[L1];
+  Er[0] = 1.f;
+  Ei[0] = 0.f;
+#pragma unroll
+  for (int m = 1; m <= LMAX; ++m) {
+    Er[m] = Er[m - 1] * g.ux - Ei[m - 1] * g.uy;
+    Ei[m] = Er[m - 1] * g.uy + Ei[m - 1] * g.ux;
+  }
+  psi = 0.f;
+  float psir = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+  float Gprev = 0.f, Gl = g.g0;
+  // Legendre factors: the ping-pong arrays of the VALU pass (degree l writes
+  // the array of its parity, reading the other one)
+  float QA[L1], QB[L1];
+#pragma unroll
+  for (int m = 0; m <= LMAX; ++m) {
+    QA[m] = (m & 1) == 0 ? 1.f : 0.f;
+    QB[m] = (m & 1) == 1 ? 1.f : 0.f;
+  }
+  static_for<0, L1>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    float(&QW)[L1] = (l & 1) ? QB : QA;
+    const float(&QR)[L1] = (l & 1) ? QA : QB;
+    float cw[S::nv(l)];
+    const float* src = img + S::off(l) * 64 + lane;
+#pragma unroll
+    for (int v = 0; v < S::nv(l); ++v) cw[v] = src[v * 64];
+    const float* tl = tab + l * S::TS;
+    if constexpr (l > 0) {
+      Gprev = Gl;
+      Gl = Gl * g.w;
+    }
+    const float dGl = float(l) * Gprev * g.om - float(2 * l + 1) * g.kap * Gl;
+    float p[NW];
+    p[0] = 1.f;
+    if constexpr (NMAXC >= 1) p[1] = g.xi;
+#pragma unroll
+    for (int n = 2; n <= NMAXC; ++n) p[n] = g.xi * p[n - 1] - tl[n] * p[n - 2];
+    float psl = 0.f, rhl = 0.f, gxl = 0.f, gyl = 0.f, gzl = 0.f;
+    float Qup = 0.f;
+    auto legendre = [&](auto mc, float& Q, float& dQ) {
+      constexpr int m = decltype(mc)::value;
+      Q = g.c * QR[m] - float(legendre_b(l, m)) * QW[m];
+      QW[m] = Q;
+      dQ = float(l - m) * Qup;
+      Qup = Q;
+    };
+    auto combine = [&](auto mc, const float Q, const float dQ, const mfma_f4 acc) {
+      constexpr int m = decltype(mc)::value;
+      const float sc = acc[0], dsc = acc[1];
+      if constexpr (m == 0) {
+        psl = fmaf(Q, sc, psl);
+        rhl = fmaf(Q, dsc, rhl);
+        gzl = fmaf(dQ, sc, gzl);
+      } else {
+        const float ss = acc[2], dss = acc[3];
+        const float v1 = sc * Er[m] + ss * Ei[m];
+        const float v2 = dsc * Er[m] + dss * Ei[m];
+        const float v3 = sc * Er[m - 1] + ss * Ei[m - 1];
+        const float v4 = ss * Er[m - 1] - sc * Ei[m - 1];
+        const float mQ = float(m) * Q;
+        psl = fmaf(Q, v1, psl);
+        rhl = fmaf(Q, v2, rhl);
+        gzl = fmaf(dQ, v1, gzl);
+        gxl = fmaf(mQ, v3, gxl);
+        gyl = fmaf(mQ, v4, gyl);
+      }
+    };
+    // the sums are due at each call: this keeps the compiler from holding
+    // every group's accumulators until the end of the sweep
+    auto sums_due = [&]() {
+      asm volatile("" : "+v"(psl), "+v"(rhl), "+v"(gzl), "+v"(gxl), "+v"(gyl));
+    };
+    // orders from m = l down, in groups of up to MFMA_GROUP whose chains
+    // interleave (independent accumulators hide the matrix-core latency)
+    static_for_down<l, MFMA_GROUP>([&](auto mc) {
+      constexpr int mt = decltype(mc)::value;  // top order of the group
+      constexpr int gs = mt + 1 < MFMA_GROUP ? mt + 1 : MFMA_GROUP;
+      float Q[gs], dQ[gs];
+      mfma_f4 acc[gs];
+      static_for<0, gs>([&](auto gc) {
+        constexpr int k = decltype(gc)::value;
+        legendre(std::integral_constant<int, mt - k>{}, Q[k], dQ[k]);
+        acc[k] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+      });
+      static_for<0, NW>([&](auto nc) {
+        constexpr int n = decltype(nc)::value;
+        static_for<0, gs>([&](auto gc) {
+          constexpr int k = decltype(gc)::value;
+          constexpr int q = (mt - k) * NW + n;
+          acc[k] = mfma_bcast<q>(cw[q >> 4], p[n], acc[k]);
+        });
+      });
+      static_for<0, gs>([&](auto gc) {
+        constexpr int k = decltype(gc)::value;
+        combine(std::integral_constant<int, mt - k>{}, Q[k], dQ[k], acc[k]);
+      });
+      sums_due();
+    });
+    psi = fmaf(Gl, psl, psi);
+    psir = fmaf(dGl, psl, fmaf(Gl * g.dxi, rhl, psir));
+    gx = fmaf(Gl, gxl, gx);
+    gy = fmaf(Gl, gyl, gy);
+    gz = fmaf(Gl, gzl, gz);
+    // likewise the degree's contribution
+    asm volatile("" : "+v"(psi), "+v"(psir), "+v"(gx), "+v"(gy), "+v"(gz));
+  });
+  const float rg = g.ux * gx + g.uy * gy + g.c * gz;
+  axv = 0.f;
+  ayv = 0.f;
+  azv = 0.f;
+  if (g.r > 0.f) {
+    axv = -(psir * g.ux + g.ir * (gx - rg * g.ux));
+    ayv = -(psir * g.uy + g.ir * (gy - rg * g.uy));
+    azv = -(psir * g.c + g.ir * (gz - rg * g.c));
+  }
+}
+
+// Persistent blocks of 256 threads: each builds the operand image once, then
+// takes the tiles of 256 particles blockIdx.x, blockIdx.x + gridDim.x, ...
+// Lanes past the end evaluate the last particle (so that every lane joins the
+// MFMAs) and store nothing.
+template <int NMAXC, int LMAX, int MODE, bool INLINE_BUILD>
+__device__ __forceinline__ void field_mfma_body(const ForceArgs<float>& a) {
+  using S = MfmaShape<NMAXC, LMAX>;
+  __shared__ __align__(16) float img[S::IMG];
+  __shared__ float tab[S::TAB];
+  if constexpr (INLINE_BUILD)
+    build_mfma_operands<NMAXC, LMAX>(img, tab, a.W, a.dtab, a.beta_rad);
+  else
+    build_mfma_operands_call<NMAXC, LMAX>(img, tab, a.W, a.dtab, a.beta_rad);
+  __syncthreads();
+  const int64_t ntiles = (a.n + 255) / 256;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t i = t * 256 + threadIdx.x;
+    const bool live = i < a.n;
+    const int64_t ic = live ? i : a.n - 1;
+    const float x = a.x[ic], y = a.y[ic], z = a.z[ic];
+    float psi, axv, ayv, azv;
+    field_eval_mfma<NMAXC, LMAX>(x, y, z, img, tab, a.binv, a.alpha, a.inv_alpha, a.amode, psi,
+                                 axv, ayv, azv);
+    if (live)
+      field_store<float, MODE>(a, i, x, y, z, psi, axv, ayv, azv, a.cx, a.cy, a.cz, a.gcx, a.gcy,
+                               a.gcz);
+  }
+}
+
+// Two register budgets: the compiler's own (the operand build is then a call,
+// so that its registers do not add to the sweep's), and one for five waves
+// per SIMD (which also keeps the accumulators in ordinary VGPRs).
+template <int NMAXC, int LMAX, int MODE>
+__global__ void __launch_bounds__(256) field_mfma_kernel(ForceArgs<float> a) {
+  field_mfma_body<NMAXC, LMAX, MODE, false>(a);
+}
+template <int NMAXC, int LMAX, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+field_mfma_kernel_o5(ForceArgs<float> a) {
+  field_mfma_body<NMAXC, LMAX, MODE, true>(a);
 }
 
 // sum over the 64 lanes of a wave (every lane receives the total)
@@ -733,13 +1052,50 @@ struct EngineImpl final : Engine {
       coef_kernel<R, NMAXC, LMAX, V::LPP[2], V::WPB[2]><<<nblocks, 64 * V::WPB[2], 0, s>>>(ca);
     return hipGetLastError();
   }
-  int field_variants() const override { return 2; }
+  // field variants: 0 and 1 = VALU kernel under two register budgets; 2 and 3
+  // (single precision) = matrix-core kernel under two register budgets, for
+  // the plain force and step passes (the batched and adjoint passes run
+  // variant 1 instead)
+  int field_variants() const override { return sizeof(R) == 4 ? 4 : 2; }
+  // resident blocks of a persistent kernel on the device
+  template <typename K>
+  static int64_t resident_blocks(K kernel) {
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+      ncu = 1;
+    return (int64_t)per_cu * ncu;
+  }
   hipError_t launch_force(const void* args, int64_t nblocks, int mode, int fv,
                           hipStream_t s) const override {
     if (nblocks <= 0) return hipSuccess;
     const ForceArgs<R>& fa = *(const ForceArgs<R>*)args;
+    if constexpr (sizeof(R) == 4) {
+      if (fv >= 2 && mode != 2 && !fa.blk_cluster) {
+        // nblocks tiles of 256 particles over at most one resident round of blocks
+        static const int64_t cap[2] = {resident_blocks(field_mfma_kernel<NMAXC, LMAX, 1>),
+                                       resident_blocks(field_mfma_kernel_o5<NMAXC, LMAX, 1>)};
+        const dim3 g((unsigned)(nblocks < cap[fv - 2] ? nblocks : cap[fv - 2]));
+        if (fv == 2) {
+          if (mode == 0)
+            field_mfma_kernel<NMAXC, LMAX, 0><<<g, 256, 0, s>>>(fa);
+          else
+            field_mfma_kernel<NMAXC, LMAX, 1><<<g, 256, 0, s>>>(fa);
+        } else {
+          if (mode == 0)
+            field_mfma_kernel_o5<NMAXC, LMAX, 0><<<g, 256, 0, s>>>(fa);
+          else
+            field_mfma_kernel_o5<NMAXC, LMAX, 1><<<g, 256, 0, s>>>(fa);
+        }
+        return hipGetLastError();
+      }
+    }
     const dim3 g((unsigned)nblocks);
-    if (fv == 1 && mode != 2) {
+    if (fv >= 1 && mode != 2) {
       if (fa.blk_cluster)
         field_kernel_o4<R, NMAXC, LMAX, 1, true><<<g, 256, 0, s>>>(fa);
       else if (mode == 0)

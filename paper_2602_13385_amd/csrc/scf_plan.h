@@ -197,6 +197,7 @@ struct scf_plan {
   double* d_cs = nullptr;
   double* d_fw = nullptr;
   double* d_kden = nullptr;  // density constants -K_nl / (4 pi G b^2), [l][n]
+  double* d_dtab = nullptr;  // radial derivative table of the matrix-core field pass, [l][2][n]
   std::vector<double> h_cs, h_fw;
   // kernel timing
   bool prof = false;
@@ -409,6 +410,7 @@ void fill_force_common(ForceArgs<R>& fa, const scf_plan* p) {
   fa.alpha = R(p->basis.alpha);
   fa.inv_alpha = R(1.0 / p->basis.alpha);
   fa.amode = p->amode;
+  fa.dtab = p->d_dtab;
 }
 
 template <typename R>
@@ -600,6 +602,28 @@ hipError_t fill_tables(scf_plan* p, const scf_basis* basis) {
       }
     if (e == hipSuccess && !p->d_kden) e = hipMalloc((void**)&p->d_kden, kd.size() * 8);
     if (e == hipSuccess) e = hipMemcpy(p->d_kden, kd.data(), kd.size() * 8, hipMemcpyHostToDevice);
+  }
+  {
+    // the xi-derivative of the monic Gegenbauer basis in the same basis:
+    // d C_n^lam / d xi = 2 lam C_{n-1}^(lam+1) = 2 sum_{k = n-1, n-3, ..} (k + lam) C_k^lam,
+    // so for p_n = C_n^lam / kappa_n (kappa_n = 2^n (lam)_n / n!, the leading
+    // coefficient) d p_n / d xi = sum_k D_nk p_k with D_nk = 2 (k + lam) kappa_k / kappa_n
+    // for odd n - k > 0.  The matrix-core field pass needs the coefficients
+    // W'_k = sum_n D_nk W_n = 2 (k + lam) kappa_k S_k, S_k = sum_{n = k+1, k+3, ..} W_n / kappa_n,
+    // a suffix sum it forms per row; stored per degree: [l][0][n] = 1 / kappa_n,
+    // [l][1][k] = 2 (k + lam) kappa_k.
+    std::vector<double> dt((size_t)L1 * 2 * NW, 0.0);
+    for (int l = 0; l <= p->lmax; ++l) {
+      const double lam = (2.0 * l + 1.0) * basis->alpha + 0.5;
+      double kap = 1.0;
+      for (int n = 0; n <= p->nmaxc; ++n) {
+        dt[((size_t)l * 2 + 0) * NW + n] = 1.0 / kap;
+        dt[((size_t)l * 2 + 1) * NW + n] = 2.0 * (n + lam) * kap;
+        kap *= 2.0 * (lam + n) / (n + 1.0);
+      }
+    }
+    if (e == hipSuccess && !p->d_dtab) e = hipMalloc((void**)&p->d_dtab, dt.size() * 8);
+    if (e == hipSuccess) e = hipMemcpy(p->d_dtab, dt.data(), dt.size() * 8, hipMemcpyHostToDevice);
   }
   return e;
 }

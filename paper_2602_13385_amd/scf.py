@@ -353,12 +353,19 @@ class Plan:
                                 _ptr(ws), ws.numel(), _stream()))
         return out
 
-    def forces(self, x, y, z, coef, host=None, centre=None, pot=False):
+    def forces(self, x, y, z, coef, host=None, centre=None, pot=False, out=None):
+        """Accelerations (and the potential with pot=True) at x, y, z; out =
+        (ax, ay, az[, pot]) names caller-owned output tensors."""
         torch = _torch()
         self._check_arrays(x, y, z)
         n = x.numel()
-        ax, ay, az = (torch.empty_like(x) for _ in range(3))
-        p = torch.empty_like(x) if pot else None
+        if out is not None:
+            ax, ay, az = out[:3]
+            p = out[3] if pot else None
+            self._check_arrays(x, ax, ay, az, *([p] if pot else []))
+        else:
+            ax, ay, az = (torch.empty_like(x) for _ in range(3))
+            p = torch.empty_like(x) if pot else None
         h = make_host(host[0], host[1]) if host is not None else None
         cen = (C.c_double * 3)(*[float(v) for v in centre[:3]]) if centre is not None else None
         ws = self.workspace(n, device=x.device)

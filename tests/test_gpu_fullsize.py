@@ -76,14 +76,22 @@ def test_headline_workload_full_size(torch, S, O, dtype):
     torch.cuda.synchronize()
     ref0 = O.coeffs(B, *st0[:3], m)
     assert coef_err(c0.cpu().numpy(), ref0) <= TOL[dtype], coef_err(c0.cpu().numpy(), ref0)
+    idx = np.linspace(0, p.n - 1, 2000).astype(int)
+    _, a0 = O.field(B, ref0, *st0[:3, idx], pot=False)
+    # every field variant at full N (the matrix-core one runs persistent
+    # blocks of several tiles each)
+    tuned = plan.field_variant
+    for fv in range(plan.num_field_variants):
+        plan.field_variant = fv
+        g = _np(plan.forces(st[0], st[1], st[2], torch.as_tensor(ref0, device="cuda")))
+        assert force_err(g[:, idx], a0) <= TOL[dtype], (fv, force_err(g[:, idx], a0))
+    plan.field_variant = tuned
     # one step; the oracle redoes it at a sample from the GPU's own positions
     dt, h = w.dt, 0.5 * w.dt
     c1 = torch.empty(plan.T, dtype=torch.float64, device="cuda")
     plan.step(st, md, dt, 1, coef_last=c1)
     torch.cuda.synchronize()
     st1 = _np(st)
-    idx = np.linspace(0, p.n - 1, 2000).astype(int)
-    _, a0 = O.field(B, ref0, *st0[:3, idx], pot=False)
     v_half = st0[3:, idx] + h * a0
     x1 = st0[:3, idx] + dt * v_half
     d = np.abs(st1[:3, idx] - x1).max() / np.abs(x1).max()

@@ -93,16 +93,19 @@ def test_coeffs_and_forces_match_oracle(torch, S, O, case, dtype):
         c = _gpu_coeffs(torch, S, plan, pos, m, dtype)
         assert coef_err(c, ref) <= TOL[dtype], (v, coef_err(c, ref))
     # forces from the reference coefficients, at a sample of the particles
+    # (a ragged count), for every field variant
     k = min(n, 2000)
     sub = pos[:, :k]
     Pref, gref = O.field(B, ref, *sub)
     x, y, z = (_dev(torch, sub[i], dtype) for i in range(3))
-    ax, ay, az, pot = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), pot=True)
-    torch.cuda.synchronize()
-    g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
-    assert force_err(g, gref) <= TOL[dtype], force_err(g, gref)
-    P = pot.cpu().numpy().astype(np.float64)
-    assert np.abs(P - Pref).max() / np.abs(Pref).max() <= TOL[dtype]
+    for fv in range(plan.num_field_variants):
+        plan.field_variant = fv
+        ax, ay, az, pot = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), pot=True)
+        torch.cuda.synchronize()
+        g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
+        assert force_err(g, gref) <= TOL[dtype], (fv, force_err(g, gref))
+        P = pot.cpu().numpy().astype(np.float64)
+        assert np.abs(P - Pref).max() / np.abs(Pref).max() <= TOL[dtype], fv
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
@@ -122,11 +125,13 @@ def test_forces_with_host_tidal_field(torch, S, O, dtype):
     gref = gscf - gh + g0[:, None]
     plan = S.Plan(10, 6, dtype=dtype)
     x, y, z = (_dev(torch, pos[i], dtype) for i in range(3))
-    ax, ay, az = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), host=(comps, 1.0),
-                             centre=centre)
-    torch.cuda.synchronize()
-    g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
-    assert force_err(g, gref) <= TOL[dtype], force_err(g, gref)
+    for fv in range(plan.num_field_variants):
+        plan.field_variant = fv
+        ax, ay, az = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), host=(comps, 1.0),
+                                 centre=centre)
+        torch.cuda.synchronize()
+        g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
+        assert force_err(g, gref) <= TOL[dtype], (fv, force_err(g, gref))
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
@@ -152,12 +157,14 @@ def test_edge_cases(torch, S, O, dtype):
     ref = O.coeffs(B, *pos, m)
     _, gref = O.field(B, ref, *pos)
     x, y, z = (_dev(torch, pos[i], dtype) for i in range(3))
-    ax, ay, az = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"))
-    torch.cuda.synchronize()
-    g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
-    assert np.isfinite(g).all()
-    assert (g[:, 0] == 0).all()  # the origin gets zero SCF force
-    assert force_err(g, gref) <= TOL[dtype]
+    for fv in range(plan.num_field_variants):
+        plan.field_variant = fv
+        ax, ay, az = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"))
+        torch.cuda.synchronize()
+        g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
+        assert np.isfinite(g).all(), fv
+        assert (g[:, 0] == 0).all(), fv  # the origin gets zero SCF force
+        assert force_err(g, gref) <= TOL[dtype], fv
 
 
 def test_coefficients_are_deterministic(torch, S):
@@ -248,24 +255,87 @@ def test_step_matches_oracle(torch, S, O, case, dtype):
     assert np.abs(out2 - out).max() <= split_tol * np.abs(out).max()
 
 
+@pytest.mark.parametrize("fv", [2, 3])
+@pytest.mark.parametrize("case", STEP_CASES, ids=lambda c: f"n{c[0]}l{c[1]}N{c[2]}")
+def test_step_with_matrix_core_field_matches_oracle(torch, S, O, case, fv):
+    """The fused kick-drift of the step (host field included) through the
+    matrix-core field variants, against the oracle's steps."""
+    nmax, lmax, n, comps, centre, dt, nsteps = case
+    print(f"[step parity, field variant {fv}] nmax={nmax} lmax={lmax} N={n}", flush=True)
+    p = I.plummer(n, 900 + nsteps)
+    st0 = _rounded(p.state(), "f32")
+    m = _rounded(p.mass, "f32")
+    B = O.basis(nmax, lmax)
+    st_ref, cen_ref, coef_ref, acc_ref = O.step(B, _ohost(O, comps), st0, m, centre, dt, nsteps,
+                                                want_acc=True)
+    plan = S.Plan(nmax, lmax, dtype="f32")
+    plan.field_variant = fv
+    st = [_dev(torch, st0[i], "f32") for i in range(6)]
+    cen, acc = plan.step(st, _dev(torch, m, "f32"), dt, nsteps,
+                         host=(comps, 1.0) if comps else None, centre=centre)
+    torch.cuda.synchronize()
+    out = np.stack([t.cpu().numpy() for t in st]).astype(np.float64)
+    a = np.stack([t.cpu().numpy() for t in acc]).astype(np.float64)
+    assert np.allclose(cen, cen_ref, rtol=0, atol=1e-12)
+    for rows in (slice(0, 3), slice(3, 6)):
+        d = np.abs(out[rows] - st_ref[rows]).max() / np.abs(st_ref[rows]).max()
+        assert d <= TOL["f32"], d
+    assert force_err(a, acc_ref) <= 2 * TOL["f32"], force_err(a, acc_ref)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_field_variants_are_bitwise_identical(torch, S, dtype):
+def test_field_variants_agree(torch, S, dtype):
+    """Each pair of variants that runs one kernel under two register budgets
+    (0 and 1 on the vector ALUs, 2 and 3 on the matrix cores in FP32) agrees
+    bitwise, and every variant is deterministic; the matrix-core pair sums in
+    another order and agrees with the vector pair to the force bar."""
     p = I.hernquist(20_000, 4242)
     plan = S.Plan(16, 10, dtype=dtype)
     x, y, z = (_dev(torch, p.pos[i], dtype) for i in range(3))
     m = _dev(torch, p.mass, dtype)
     c = plan.coeffs(x, y, z, m)
+    nv = plan.num_field_variants
+    assert nv == (4 if dtype == "f32" else 2)
     outs = []
-    for v in range(plan.num_field_variants):
+    for v in list(range(nv)) + [nv - 1]:
         plan.field_variant = v
         outs.append(plan.forces(x, y, z, c, host=([("nfw", (232.98, 20.0))], 1.0),
                                 centre=[20.0, 1.0, -2.0]))
     torch.cuda.synchronize()
-    for o in outs[1:]:
-        for a, b in zip(o, outs[0]):
-            assert torch.equal(a, b)
+    for i, j in [(0, 1), (nv, nv - 1)] + ([(2, 3)] if nv > 2 else []):
+        for a, b in zip(outs[i], outs[j]):
+            assert torch.equal(a, b), (i, j)
+    if nv > 2:
+        g0 = np.stack([t.cpu().numpy() for t in outs[0]]).astype(np.float64)
+        g2 = np.stack([t.cpu().numpy() for t in outs[2]]).astype(np.float64)
+        assert force_err(g2, g0) <= TOL[dtype], force_err(g2, g0)
     plan.autotune(x, y, z, m)
-    assert 0 <= plan.field_variant < plan.num_field_variants
+    assert 0 <= plan.field_variant < nv
+
+
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 255, 257, 1000])
+def test_matrix_core_field_small_and_ragged_counts(torch, S, O, n):
+    """Every lane of a wave joins the matrix-core chains; lanes past the end
+    evaluate the last particle and store nothing."""
+    p = I.plummer(max(n, 2), 900 + n)
+    pos = _rounded(p.pos[:, :n], "f32")
+    B = O.basis(10, 6)
+    ref = O.coeffs(B, *_rounded(p.pos, "f32"), _rounded(p.mass, "f32"))
+    Pref, gref = O.field(B, ref, *pos)
+    plan = S.Plan(10, 6, dtype="f32")
+    x, y, z = (_dev(torch, pos[i], "f32") for i in range(3))
+    for fv in (2, 3):
+        plan.field_variant = fv
+        guard = torch.full((n + 64,), 7.0, dtype=torch.float32, device="cuda")
+        ax = guard[:n]
+        ay, az, pot = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
+        plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), pot=True,
+                    out=(ax, ay, az, pot))
+        torch.cuda.synchronize()
+        g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
+        assert force_err(g, gref) <= TOL["f32"], (fv, force_err(g, gref))
+        assert np.abs(pot.cpu().numpy() - Pref).max() / np.abs(Pref).max() <= TOL["f32"], fv
+        assert (guard[n:].cpu().numpy() == 7.0).all(), fv
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
