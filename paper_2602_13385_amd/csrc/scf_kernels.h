@@ -777,10 +777,7 @@ __device__ __forceinline__ void field_eval_mfma(const float x, const float y, co
     constexpr int l = decltype(lc)::value;
     float(&QW)[L1] = (l & 1) ? QB : QA;
     const float(&QR)[L1] = (l & 1) ? QA : QB;
-    float cw[S::nv(l)];
     const float* src = img + S::off(l) * 64 + lane;
-#pragma unroll
-    for (int v = 0; v < S::nv(l); ++v) cw[v] = src[v * 64];
     const float* tl = tab + l * S::TS;
     if constexpr (l > 0) {
       Gprev = Gl;
@@ -832,6 +829,11 @@ __device__ __forceinline__ void field_eval_mfma(const float x, const float y, co
     static_for_down<l, MFMA_GROUP>([&](auto mc) {
       constexpr int mt = decltype(mc)::value;  // top order of the group
       constexpr int gs = mt + 1 < MFMA_GROUP ? mt + 1 : MFMA_GROUP;
+      // the operand registers this group's quadruples lie in, from LDS
+      constexpr int vlo = ((mt - gs + 1) * NW) >> 4, vhi = (mt * NW + NMAXC) >> 4;
+      float cw[vhi - vlo + 1];
+#pragma unroll
+      for (int v = vlo; v <= vhi; ++v) cw[v - vlo] = src[v * 64];
       float Q[gs], dQ[gs];
       mfma_f4 acc[gs];
       static_for<0, gs>([&](auto gc) {
@@ -844,7 +846,7 @@ __device__ __forceinline__ void field_eval_mfma(const float x, const float y, co
         static_for<0, gs>([&](auto gc) {
           constexpr int k = decltype(gc)::value;
           constexpr int q = (mt - k) * NW + n;
-          acc[k] = mfma_bcast<q>(cw[q >> 4], p[n], acc[k]);
+          acc[k] = mfma_bcast<q>(cw[(q >> 4) - vlo], p[n], acc[k]);
         });
       });
       static_for<0, gs>([&](auto gc) {
