@@ -47,11 +47,13 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-@pytest.mark.parametrize("dtype,host", [("f64", True), ("f32", True), ("f64", False),
-                                        ("f32", False)])
-def test_adjoint_matches_oracle(torch, S, O, dtype, host):
+# fv: the plan's field variant (3 = the matrix-core field pass of FP32 plans,
+# which the segment's forward recompute uses)
+@pytest.mark.parametrize("dtype,host,fv", [("f64", True, 0), ("f32", True, 0), ("f64", False, 0),
+                                           ("f32", False, 0), ("f32", True, 3)])
+def test_adjoint_matches_oracle(torch, S, O, dtype, host, fv):
     n, nmax, lmax, dt, nsteps = 3000, 10, 6, 0.005, 4
-    print(f"[adjoint parity] {dtype} host={host}", flush=True)
+    print(f"[adjoint parity] {dtype} host={host} field variant {fv}", flush=True)
     p = I.plummer(n, 5501)
     st0 = _rounded(p.state(), dtype)
     m = _rounded(p.mass, dtype)
@@ -63,6 +65,7 @@ def test_adjoint_matches_oracle(torch, S, O, dtype, host):
     cen = CEN if host else np.zeros(6)
     lam_ref, lc_ref, gh_ref = O.step_adjoint(B, Ho, st0, m, cen, dt, nsteps, lam, lamc)
     plan = S.Plan(nmax, lmax, dtype=dtype)
+    plan.field_variant = fv
     st = [_dev(torch, st0[i], dtype) for i in range(6)]
     lt = [_dev(torch, lam[i], dtype) for i in range(6)]
     lc, gh = plan.step_adjoint(st, _dev(torch, m, dtype), dt, nsteps, lt, lamc,

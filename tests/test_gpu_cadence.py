@@ -72,15 +72,17 @@ def _rel(a, ref):
     return np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_step_frozen_matches_oracle(torch, S, O, dtype):
-    print(f"[cadence] step_frozen {dtype}", flush=True)
+# field variants: 0 = vector-ALU field pass, 3 = matrix-core one (FP32 plans)
+@pytest.mark.parametrize("dtype,fv", [("f32", 0), ("f32", 3), ("f64", 0)])
+def test_step_frozen_matches_oracle(torch, S, O, dtype, fv):
+    print(f"[cadence] step_frozen {dtype} field variant {fv}", flush=True)
     st0, m = _cluster(3000, 21, 1.0, dtype)
     B = O.basis(10, 6)
     coef = O.coeffs(B, *st0[:3], m)
     cen0 = np.array([20.0, 0.0, 0.0, 0.0, I.LOG_VC_20, 0.0])
     ref, cref = O.step_frozen(B, _ohost(O, LOG_HOST), st0, coef, cen0, 0.01, 10)
     plan = S.Plan(10, 6, dtype=dtype)
+    plan.field_variant = fv
     st = [_dev(torch, st0[i], dtype) for i in range(6)]
     c = torch.as_tensor(coef, dtype=torch.float64, device="cuda")
     cen, acc = plan.step_frozen(st, c, 0.01, 6, host=(LOG_HOST, 1.0), centre=cen0)
@@ -92,12 +94,13 @@ def test_step_frozen_matches_oracle(torch, S, O, dtype):
     assert np.abs(cen - cref).max() <= 1e-12 * np.abs(cref).max()
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("dtype,fv", [("f32", 0), ("f32", 3), ("f64", 0)])
 @pytest.mark.parametrize("n,vscale,frac", [(5000, 1.25, 0.999), (5000, 1.25, 0.9),
                                            (4000, 1.0, 1.0), (7, 1.0, 0.5), (1, 0.5, 0.999),
                                            (3000, 1000.0, 0.999)])
-def test_select_matches_oracle(torch, S, O, dtype, n, vscale, frac):
-    print(f"[cadence] select {dtype} n={n} vscale={vscale} frac={frac}", flush=True)
+def test_select_matches_oracle(torch, S, O, dtype, fv, n, vscale, frac):
+    print(f"[cadence] select {dtype} field variant {fv} n={n} vscale={vscale} frac={frac}",
+          flush=True)
     st0, m = _cluster(n, 5 + n, vscale, dtype)
     B = O.basis(10, 6)
     coef = O.coeffs(B, *st0[:3], m)
@@ -106,6 +109,7 @@ def test_select_matches_oracle(torch, S, O, dtype, n, vscale, frac):
     # bound test depends on the two potentials
     assert info["emargin"] > MARGIN[dtype]
     plan = S.Plan(10, 6, dtype=dtype)
+    plan.field_variant = fv
     st = [_dev(torch, st0[i], dtype) for i in range(6)]
     md = _dev(torch, m, dtype)
     c = torch.as_tensor(coef, dtype=torch.float64, device="cuda")
@@ -162,14 +166,16 @@ def test_cadence_init_matches_oracle(torch, S, O, dtype):
     assert _rel(coef.cpu().numpy(), coef_ref) <= TOL[dtype]
 
 
-@pytest.mark.parametrize("dtype,nint,every,dt_max,nsamp", [("f64", 7, 3, 0.05, 8),
-                                                          ("f32", 4, 2, 0.1, 12),
-                                                          ("f64", 3, 5, 0.05, 0)])
-def test_evolve_matches_oracle(torch, S, O, dtype, nint, every, dt_max, nsamp):
+@pytest.mark.parametrize("dtype,nint,every,dt_max,nsamp,fv", [("f64", 7, 3, 0.05, 8, 0),
+                                                             ("f32", 4, 2, 0.1, 12, 0),
+                                                             ("f32", 4, 2, 0.1, 12, 3),
+                                                             ("f64", 3, 5, 0.05, 0, 0)])
+def test_evolve_matches_oracle(torch, S, O, dtype, nint, every, dt_max, nsamp, fv):
     """Plummer (N = 2000) at R = 20 in the logarithmic host, with speeds
     scaled so that particles escape: the interval log, the weights, the state,
     the centre and the coefficients after every run."""
-    print(f"[cadence] evolve {dtype} nint={nint} every={every} samples/tdyn={nsamp}", flush=True)
+    print(f"[cadence] evolve {dtype} nint={nint} every={every} samples/tdyn={nsamp} "
+          f"field variant {fv}", flush=True)
     st0, m = _cluster(2000, 77, 1.15, dtype)
     B = O.basis(10, 6)
     H = _ohost(O, LOG_HOST)
@@ -188,6 +194,7 @@ def test_evolve_matches_oracle(torch, S, O, dtype, nint, every, dt_max, nsamp):
     if nsamp:
         assert any(e["nsamples"] > 1 for e in log_ref)
     plan = S.Plan(10, 6, dtype=dtype)
+    plan.field_variant = fv
     st = [_dev(torch, st0[i], dtype) for i in range(6)]
     md = _dev(torch, m, dtype)
     coef, w, state = plan.cadence_init(st, md, 0.999)
