@@ -415,11 +415,13 @@ scf_status scf_autotune(scf_plan* plan, int64_t n, const void* x, const void* y,
  * persistent blocks, again under two register budgets (the compiler's own, or
  * 5 waves per SIMD); these two agree bitwise with each other and, since they
  * sum in another order, with variants 0 and 1 to the single-precision force
- * tolerance.  The batched and adjoint passes run variant 1's kernel whenever
- * a variant >= 1 is set.  scf_autotune_field computes the coefficients of
- * the given particles, times each variant on the forces at those particles
- * (written to ax, ay, az, device, caller-owned; synchronising the stream) and
- * keeps the fastest for the plan; best_ms (nullable) receives its time. */
+ * tolerance.  The batched step runs variant 1's kernel for variants 2 and 3
+ * (its per-cluster blocks measured faster on the vector ALUs), and the
+ * adjoint's accumulation pass always runs variant 0's.  scf_autotune_field
+ * computes the coefficients of the given particles, times each variant on
+ * the forces at those particles (written to ax, ay, az, device, caller-owned;
+ * synchronising the stream) and keeps the fastest for the plan; best_ms
+ * (nullable) receives its time. */
 int32_t scf_plan_num_field_variants(const scf_plan* plan);
 int32_t scf_plan_field_variant(const scf_plan* plan);
 scf_status scf_plan_set_field_variant(scf_plan* plan, int32_t variant);

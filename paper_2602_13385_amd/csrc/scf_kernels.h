@@ -1056,8 +1056,8 @@ struct EngineImpl final : Engine {
   }
   // field variants: 0 and 1 = VALU kernel under two register budgets; 2 and 3
   // (single precision) = matrix-core kernel under two register budgets, for
-  // the plain force and step passes (the batched and adjoint passes run
-  // variant 1 instead)
+  // the plain force and step passes (the batched step runs variant 1's kernel
+  // for them, the adjoint's accumulation pass variant 0's)
   int field_variants() const override { return sizeof(R) == 4 ? 4 : 2; }
   // resident blocks of a persistent kernel on the device
   template <typename K>

@@ -81,16 +81,19 @@ def _run(torch, S, plan, off, st0, m, cens, dtype, dt, nsteps, graph=False, coef
     return out, cen, a
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_batched_matches_oracle(torch, S, O, dtype):
+# fv: the plan's field variant (the batched step runs variant 1's kernel for the
+# matrix-core variants 2 and 3 of FP32 plans)
+@pytest.mark.parametrize("dtype,fv", [("f32", 0), ("f32", 2), ("f32", 3), ("f64", 0)])
+def test_batched_matches_oracle(torch, S, O, dtype, fv):
     sizes = [3000, 0, 11000, 6173, 1]
-    print(f"[batched parity] sizes={sizes} {dtype}", flush=True)
+    print(f"[batched parity] sizes={sizes} {dtype} field variant {fv}", flush=True)
     off, st0, m, cens = _clusters(sizes, 4401)
     st0, m = _rounded(st0, dtype), _rounded(m, dtype)
     dt, nsteps = 0.005, 4
     B = O.basis(10, 6)
     st_ref, cen_ref, coef_ref = O.step_batched(B, _ohost(O), off, st0, m, cens, dt, nsteps)
     plan = S.Plan(10, 6, dtype=dtype)
+    plan.field_variant = fv
     coef = torch.empty(len(sizes) * plan.T, dtype=torch.float64, device="cuda")
     out, cen, _ = _run(torch, S, plan, off, st0, m, cens, dtype, dt, nsteps, coef=coef)
     assert np.abs(cen - cen_ref).max() <= 1e-12
@@ -112,13 +115,15 @@ def test_batched_matches_oracle(torch, S, O, dtype):
         assert e <= tol, (c, e)
 
 
-def test_batched_graph_replays_equal_eager(torch, S):
+@pytest.mark.parametrize("fv", [0, 3])
+def test_batched_graph_replays_equal_eager(torch, S, fv):
     """Every graph replay equals the directly launched kernels bitwise,
     across several calls with other GPU work and host synchronisation in
     between; the graph is captured once for the repeated argument set."""
     sizes = [5000, 2500, 9000]
     off, st0, m, cens = _clusters(sizes, 4402)
     plan = S.Plan(10, 6, dtype="f32")
+    plan.field_variant = fv
     md = _dev(torch, m, "f32")
     sg = [_dev(torch, st0[i], "f32") for i in range(6)]
     se = [_dev(torch, st0[i], "f32") for i in range(6)]
@@ -160,12 +165,13 @@ def test_batched_eight_step_graphs_across_centre_chunks(torch, S):
     assert plan.graph_captures == 1
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_batched_equals_plain_per_cluster(torch, S, dtype):
+@pytest.mark.parametrize("dtype,fv", [("f32", 0), ("f32", 3), ("f64", 0)])
+def test_batched_equals_plain_per_cluster(torch, S, dtype, fv):
     sizes = [4000, 7000]
     off, st0, m, cens = _clusters(sizes, 4403)
     dt, nsteps = 0.005, 3
     plan = S.Plan(10, 6, dtype=dtype)
+    plan.field_variant = fv
     out, cen, acc = _run(torch, S, plan, off, st0, m, cens, dtype, dt, nsteps)
     tol = 1e-6 if dtype == "f32" else 1e-13
     for c in range(len(sizes)):
