@@ -96,8 +96,10 @@ def _timed(torch, fn):
     return out, e0.elapsed_time(e1)
 
 
-def run_main(dtype, steps, warmup, torch, scf, I, profile):
-    """Hernquist N = 1e6, nmax 16, lmax 10: `steps` timed steps."""
+def run_main(dtype, steps, warmup, torch, scf, I, profile, variants=None):
+    """Hernquist N = 1e6, nmax 16, lmax 10: `steps` timed steps.  variants =
+    (coefficient variant, field variant) pins the kernels instead of the
+    autotuner's choice (for profiles of one fixed kernel pair)."""
     w = I.config3()
     p = w.clusters[0]
     td = torch.float32 if dtype == "f32" else torch.float64
@@ -105,7 +107,11 @@ def run_main(dtype, steps, warmup, torch, scf, I, profile):
     st = [dev(p.state()[i]) for i in range(6)]
     m = dev(p.mass)
     plan = scf.Plan(w.nmax, w.lmax, alpha=w.alpha, b=w.b, G=w.G, dtype=dtype)
-    variant, _ = plan.autotune(st[0], st[1], st[2], m)
+    if variants is None:
+        variant, _ = plan.autotune(st[0], st[1], st[2], m)
+    else:
+        variant, plan.variant = variants[0], variants[0]
+        plan.field_variant = variants[1]
     n = p.n
     cen, acc = plan.step(st, m, w.dt, 1)  # start-up evaluation of a(x0)
     if warmup:
@@ -144,16 +150,22 @@ def accuracy_main(torch, scf, I):
         m = torch.as_tensor(mass, dtype=td, device="cuda")
         plan = scf.Plan(w.nmax, w.lmax, dtype=dtype)
         c = plan.coeffs(x, y, z, m)
-        ax, ay, az, pot = plan.forces(x, y, z, c, pot=True)
-        torch.cuda.synchronize()
-        res[dtype] = (c.cpu().numpy(), np.stack([t.double().cpu().numpy() for t in (ax, ay, az)]),
-                      pot.double().cpu().numpy())
+        # forces from every field variant (FP32: 0, 1 vector ALU; 2, 3 matrix cores)
+        gs = []
+        for fv in range(plan.num_field_variants):
+            plan.field_variant = fv
+            ax, ay, az, pot = plan.forces(x, y, z, c, pot=True)
+            torch.cuda.synchronize()
+            gs.append(np.stack([t.double().cpu().numpy() for t in (ax, ay, az)]))
+        res[dtype] = (c.cpu().numpy(), gs, pot.double().cpu().numpy())
     c32, g32, _ = res["f32"]
     c64, g64, p64 = res["f64"]
+    g64 = g64[0]
     out["coef_relerr_f32_vs_f64"] = float(np.abs(c32 - c64).max() / np.abs(c64).max())
     mag = np.sqrt((g64 ** 2).sum(0))
-    d = np.sqrt(((g32 - g64) ** 2).sum(0))
-    out["force_relerr_f32_vs_f64"] = float((d / (mag + np.median(mag))).max())
+    errs = [float((np.sqrt(((g - g64) ** 2).sum(0)) / (mag + np.median(mag))).max()) for g in g32]
+    out["force_relerr_f32_vs_f64"] = max(errs)
+    out["force_relerr_f32_vs_f64_per_field_variant"] = errs
     r = np.sqrt((np.asarray(p.pos) ** 2).sum(0))
     ref = -1.0 / (1.0 + r)
     out["pot_relerr_f64_vs_closed_form_median"] = float(np.median(np.abs(p64 - ref) / np.abs(ref)))
@@ -509,6 +521,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default=None, metavar="COEF,FIELD",
+                    help="pin the headline run's coefficient and field kernel variants "
+                         "instead of autotuning them (profiling runs)")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (f64, accuracy, batched, adjoint, long, "
@@ -541,7 +556,8 @@ def main():
         return
     scf.lib()
     print("[bench] headline FP32", file=sys.stderr, flush=True)
-    r = run_main("f32", args.steps, args.warmup, torch, scf, I, profile=True)
+    pinned = tuple(int(v) for v in args.variants.split(",")) if args.variants else None
+    r = run_main("f32", args.steps, args.warmup, torch, scf, I, profile=True, variants=pinned)
     dev = device_info(torch)  # the clock level right after the headline runs
     n, T = r["n"], r["T"]
     ms_per_step = r["ms"] / args.steps
