@@ -64,6 +64,8 @@ CASES = [  # (nmax, lmax, alpha, n, generator)
     (16, 10, 1.0, 30_001, "hernquist"),
     (10, 5, 1.0, 4_099, "ball"),
     (8, 3, 1.0, 3_001, "ball"),  # generic instance (runtime nmax < compiled bound)
+    (20, 10, 1.0, 2_003, "hernquist"),  # generic instance at its compiled bound
+    (12, 0, 1.0, 1_001, "plummer"),  # monopole only (generic, lmax 0)
     (6, 4, 0.5, 5_003, "plummer"),
     (10, 6, 0.8, 5_003, "plummer"),
 ]
