@@ -615,20 +615,23 @@ field_kernel_o4(ForceArgs<R> a) {
 // ---------------------------------------------------------------------------
 // field pass on the matrix cores (single precision)
 // ---------------------------------------------------------------------------
-// For one (l, m) the field needs four radial sums over n: sigma_c = sum_n W^c_n
-// p_n, sigma_s likewise, and their xi-derivatives.  The derivative of the monic
-// Gegenbauer basis is again a combination of that basis, d p_n / d xi =
-// sum_k D_nk p_k, so the derivatives are sums over the same p_k with the
-// coefficients W'_k = sum_n D_nk W_n.  The four sums of a wave's 64 particles
-// are then one chain of 4x4x1 16-block FP32 MFMAs over n: the A operand is the
-// coefficient quadruple (W^c, W'^c, W^s, W'^s)_n broadcast from one block, the
-// B operand is each lane's own p_n, and row r of the product lands in result
-// register r of that lane.  The quadruples live in LDS in register layout: for
-// degree l, quadruple q = m NW + n is block q % 16 (lanes 4 (q % 16) + r) of
-// register q / 16, so a degree's operands are NV coalesced LDS reads per lane
-// and every MFMA names its block as an immediate.  The Legendre recurrence,
-// the radial recurrence and the angular combination stay on the VALU, where
-// they overlap with the matrix-core chains of the other waves.
+// Same sums as field_eval (Eq. total_potential and its gradient).  For one
+// (l, m) the field needs four radial sums over n: sigma_c = sum_n W^c_n p_n,
+// sigma_s likewise, and their xi-derivatives.  The derivative of the monic
+// Gegenbauer basis is again a combination of that basis (from
+// d C_n^lam / d xi = 2 lam C_{n-1}^(lam+1) = 2 sum_{k = n-1, n-3, ..} (k + lam)
+// C_k^lam), d p_n / d xi = sum_k D_nk p_k, so the derivatives are sums over
+// the same p_k with the coefficients W'_k = sum_n D_nk W_n.  The four sums of a
+// wave's 64 particles are then one chain of 4x4x1 16-block FP32 MFMAs over n:
+// the A operand is the coefficient quadruple (W^c, W'^c, W^s, W'^s)_n
+// broadcast from one block, the B operand is each lane's own p_n, and row r of
+// the product lands in result register r of that lane.  The quadruples live in
+// LDS in register layout: for degree l, quadruple q = m NW + n is block q % 16
+// (lanes 4 (q % 16) + r) of register q / 16, so an order group's operands are
+// a few coalesced LDS reads per lane and every MFMA names its block as an
+// immediate.  The Legendre recurrence, the radial recurrence and the angular
+// combination stay on the VALU.  (On gfx950 the MFMA and VALU work of one SIMD
+// does not co-execute here, so the kernel's time is about the sum of the two.)
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
 // orders whose accumulation chains one wave interleaves
