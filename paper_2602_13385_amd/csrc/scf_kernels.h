@@ -50,7 +50,11 @@ struct CoefShape {
   static constexpr int LPP = LPP_;
   static constexpr int P = 64 / LPP;
   static constexpr int NR = NMAXC + 1;
-  static constexpr int ACC_MAX = sizeof(R) == 4 ? 96 : 64;
+  // accumulators per lane: 96 for float and double (the double kernels run
+  // at one wave per SIMD either way, and the wider tiles fill more lanes:
+  // 192 against 240 us at nmax 16, lmax 10), 64 for the dual numbers of the
+  // adjoint's gamma pass
+  static constexpr int ACC_MAX = (sizeof(R) == 4 || std::is_same<R, double>::value) ? 96 : 64;
   struct Pick {
     int jt, g, kt;
   };
