@@ -35,6 +35,22 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak: dense MFMA, and vector c
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
 METRIC = "particle×basis-term evals/s per step (FP32 vs FP64); adjoint/forward time ratio"
+# The paper's own timings: whole 5 Gyr simulations on other hardware, with its
+# relaxation, refreshes and diagnostics included, so context for the scale of
+# the problem rather than a figure to compare a per-step kernel rate with
+# (Sec. Results, opening; Appendix "Comparisons to N-body Simulations",
+# Technical Details).
+PAPER_CONTEXT = {
+    "krios_wall_clock_hr": [6.6, 6.6, 21.1],
+    "krios_hardware": "128 CPU cores",
+    "krios_workload": "N = 5e4 King W0 = 5 cluster, M = 1e5 Msun, r_hm = 10 pc, MWPotential2014, "
+                      "three orbits (20 kpc circular, eccentric, 5 kpc circular), 5 Gyr",
+    "nbody6pp_gpu_wall_clock_hr": [29, 38, 56],
+    "nbody6pp_gpu_hardware": "40-core node with one NVIDIA V100",
+    "krios_n2e5_wall_clock_hr": {"min": 5.9, "median": 11, "max": 22.1},
+    "krios_n2e5_hardware": "192 CPU cores",
+    "note": "whole-simulation wall clock on other hardware; not comparable to a per-step rate",
+}
 KERNEL_FILES = ("scf_kernels.h", "scf_device.h", "scf_dual.h", "host_field.h")
 
 
@@ -632,6 +648,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline()
     else:
         out["cpu_baseline"] = None
+    out["paper_context"] = PAPER_CONTEXT
     out["device"] = dev
     print(json.dumps(out))
 
