@@ -125,9 +125,14 @@ def test_set_basis_equals_a_new_plan(torch, S, dtype):
     c1 = plan.coeffs(st[0], st[1], st[2], m)
     c2 = ref.coeffs(st[0], st[1], st[2], m)
     assert torch.equal(c1, c2)
-    a1 = plan.forces(st[0], st[1], st[2], c1)
-    a2 = ref.forces(st[0], st[1], st[2], c2)
-    assert all(torch.equal(u, v) for u, v in zip(a1, a2))
+    # every field variant (the matrix-core ones read the derivative table
+    # that set_basis rebuilds)
+    for fv in range(plan.num_field_variants):
+        plan.field_variant = fv
+        ref.field_variant = fv
+        a1 = plan.forces(st[0], st[1], st[2], c1)
+        a2 = ref.forces(st[0], st[1], st[2], c2)
+        assert all(torch.equal(u, v) for u, v in zip(a1, a2)), fv
 
 
 def test_evolve_with_retune_matches_oracle(torch, S, O):
