@@ -308,6 +308,29 @@ def run_long(torch, scf, I):
     return out
 
 
+def run_n_scaling(torch, scf, I, sizes=(100_000, 1_000_000, 10_000_000), steps=10):
+    """The headline step (Hernquist, nmax 16, lmax 10, FP32, autotuned
+    kernels) at several particle counts on the one GPU: throughput as N
+    grows, with the field variant the autotuner picks at each size."""
+    import numpy as np
+    out = []
+    for n in sizes:
+        p = I.hernquist(n, 13385 + 3)
+        st = [torch.as_tensor(np.ascontiguousarray(p.state()[i]), dtype=torch.float32,
+                              device="cuda") for i in range(6)]
+        m = torch.as_tensor(p.mass, dtype=torch.float32, device="cuda")
+        plan = scf.Plan(16, 10, dtype="f32")
+        plan.autotune(st[0], st[1], st[2], m)
+        cen, acc = plan.step(st, m, 0.005, 2)
+        (cen, acc), ms = _timed(torch, lambda: plan.step(st, m, 0.005, steps, centre=cen, acc=acc))
+        out.append({"N": n, "ms_per_step": ms / steps, "value": n * plan.T * steps / (ms * 1e-3),
+                    "coef_variant": plan.variant, "field_variant": plan.field_variant})
+        del st, m, plan, acc
+        torch.cuda.empty_cache()
+    return {"workload": "hernquist-n16l10 at several N (FP32 step, autotuned)", "steps": steps,
+            "sizes": out}
+
+
 def run_cadence(torch, scf, I, nint=10):
     """Refresh cadence (Sec. 2.2) on the log-host workload (Plummer N = 1e5
     at R = 20, nmax 10, lmax 6, FP32): integration intervals from the tidal
@@ -543,7 +566,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (f64, accuracy, batched, adjoint, long, "
-                         "diagnostics, cadence) or 'all'")
+                         "diagnostics, cadence, nscaling) or 'all'")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline FP32 workload only (no FP64, batched, adjoint, accuracy)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -618,7 +641,8 @@ def main():
         "step_frac": step_tf / PEAK_FP32_TFLOPS,
     }
     del r["plan"]
-    legs = set(("f64", "accuracy", "batched", "adjoint", "long", "diagnostics", "cadence")
+    legs = set(("f64", "accuracy", "batched", "adjoint", "long", "diagnostics", "cadence",
+                "nscaling")
                if args.legs == "all" else args.legs.split(","))
     if args.no_f64:
         legs.discard("f64")
@@ -638,7 +662,8 @@ def main():
                    ("adjoint", "adjoint", lambda: run_adjoint(torch, scf, I)),
                    ("long", "long runs", lambda: run_long(torch, scf, I)),
                    ("diagnostics", "diagnostics", lambda: run_diagnostics(torch, scf, I)),
-                   ("cadence", "cadence", lambda: run_cadence(torch, scf, I))]
+                   ("cadence", "cadence", lambda: run_cadence(torch, scf, I)),
+                   ("nscaling", "N scaling", lambda: run_n_scaling(torch, scf, I))]
         for key, label, fn in legs_fn:
             if key in legs:
                 print(f"[bench] {label}", file=sys.stderr, flush=True)
