@@ -700,6 +700,7 @@ __device__ __forceinline__ void build_mfma_operands(float* img, float* tab,
   using S = MfmaShape<NMAXC, LMAX>;
   constexpr int NW = S::NW;
   static_assert(S::IMG % 4 == 0, "operand image in float4 units");
+  static_assert(S::L1 * S::L1 <= 256, "one thread of the 256-thread block per (l, j) row");
   for (int e = threadIdx.x; e < S::IMG / 4; e += blockDim.x)
     reinterpret_cast<float4*>(img)[e] = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int e = threadIdx.x; e < S::TAB; e += blockDim.x) {
