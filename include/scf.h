@@ -186,6 +186,26 @@ scf_status scf_step_adjoint(scf_plan* plan, int64_t n, const void* x0, const voi
                             int32_t nsteps, void* const* lam, double* lam_centre,
                             double* grad_host, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): scf_step
+ * with no workspace argument.  The workspace is a file-scope device array of
+ * scf_noalloc_scratch_bytes() bytes (64 MiB) that every GPU the library runs
+ * on holds until the process ends; its device address is looked up once per
+ * device on the first call there.  The call allocates nothing.  Arguments,
+ * state, results and errors are those of scf_step; in addition the call
+ * returns SCF_ERR_WORKSPACE, with nothing enqueued, when the plan's step
+ * needs more than the array holds (scf_workspace_size's single-cluster figure
+ * for this n, which stops growing once n covers one resident round of the
+ * coefficient pass), and SCF_ERR_INVALID_ARG when the current device is not
+ * the plan's.  All calls on one GPU share the array: calls that overlap on
+ * one GPU (other host threads, or streams without ordering between them) race
+ * on it. */
+size_t scf_noalloc_scratch_bytes(void);
+scf_status scf_step_noalloc(scf_plan* plan, int64_t n, void* x, void* y, void* z, void* vx,
+                            void* vy, void* vz, const void* m, void* ax, void* ay, void* az,
+                            uint32_t step_flags, const scf_host* host, double* centre, double dt,
+                            int32_t nsteps, double* coef_last, void* stream);
+
 /* Workspace bytes for scf_step_adjoint (grows with n * nsteps: the segment's
  * positions are kept on the device). */
 scf_status scf_adjoint_workspace_size(const scf_plan* plan, int64_t n, int32_t nsteps,

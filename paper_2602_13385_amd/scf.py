@@ -121,6 +121,10 @@ SIGNATURES = {
     "scf_step": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                            C.c_uint32, C.POINTER(CHost), _dp, C.c_double, C.c_int32, _vp, _vp,
                            C.c_size_t, _vp]),
+    "scf_noalloc_scratch_bytes": (C.c_size_t, []),
+    "scf_step_noalloc": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, C.c_uint32, C.POINTER(CHost), _dp, C.c_double, C.c_int32,
+                                   _vp, _vp]),
     "scf_step_batched": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), _vp, _vp, _vp, _vp, _vp,
                                    _vp, _vp, _vp, _vp, _vp, C.c_uint32, C.POINTER(CHost), _dp,
                                    C.c_double, C.c_int32, _vp, _vp, C.c_size_t, _vp]),
@@ -392,6 +396,23 @@ class Plan:
                               STEP_ACC_VALID if acc_valid else 0,
                               C.byref(h) if h is not None else None, C.cast(cen, _dp), float(dt),
                               int(nsteps), _ptr(coef_last), _ptr(ws), ws.numel(), _stream()))
+        return np.array(cen[:]), acc
+
+    def step_noalloc(self, st, m, dt, nsteps, host=None, centre=None, acc=None, coef_last=None):
+        """step() through scf_step_noalloc: the library's static device scratch
+        replaces the workspace, so nothing is allocated for it."""
+        torch = _torch()
+        self._check_arrays(*st, m)
+        n = st[0].numel()
+        acc_valid = acc is not None
+        if acc is None:
+            acc = [torch.empty_like(st[0]) for _ in range(3)]
+        cen = (C.c_double * 6)(*[float(v) for v in (centre if centre is not None else np.zeros(6))])
+        h = make_host(host[0], host[1]) if host is not None else None
+        _check(lib().scf_step_noalloc(self._h, n, *[_ptr(t) for t in st], _ptr(m),
+                                      *[_ptr(t) for t in acc], STEP_ACC_VALID if acc_valid else 0,
+                                      C.byref(h) if h is not None else None, C.cast(cen, _dp),
+                                      float(dt), int(nsteps), _ptr(coef_last), _stream()))
         return np.array(cen[:]), acc
 
     def adjoint_workspace(self, n, nsteps, device=None):
