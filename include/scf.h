@@ -119,8 +119,12 @@ scf_status scf_workspace_size(const scf_plan* plan, int64_t n, int32_t nclusters
 
 /* Coefficients of Eq. (sumanlm): coef (device, ncoef doubles) receives
  * a_nlm = -sum_k m_k U_nl(r_k) conj(Y_lm), about the origin of x, y, z.
- * The particle sum is accumulated in the plan's dtype over bounded runs of
- * particles and combined across thread blocks in double precision. */
+ * Single-precision plans accumulate each lane's terms in single precision
+ * over at most 16 stages of its thread block (about 150 particles at nmax 16,
+ * lmax 10, whatever n is), then add the block's sums into a (hi, lo) pair of
+ * single-precision partials with an error-free two-sum; double-precision
+ * plans accumulate in double precision.  The partials of all blocks are
+ * summed in double precision in a fixed order. */
 scf_status scf_coeffs(scf_plan* plan, int64_t n, const void* x, const void* y, const void* z,
                       const void* m, double* coef, void* ws, size_t ws_bytes, void* stream);
 
@@ -407,10 +411,12 @@ scf_status scf_tune_basis(scf_plan* plan, int64_t n, const void* x, const void* 
 scf_status scf_plan_set_basis(scf_plan* plan, double alpha, double b);
 scf_status scf_plan_get_basis(const scf_plan* plan, scf_basis* out);
 
-/* Launch configuration.  The coefficient kernel has several compiled
- * variants (lanes per particle in the basis phase, waves per block), and its
- * grid is one resident round of wave-units divided by 1, 2, 4 or 8 (fewer,
- * longer units amortise their set-up and partial row when n is small).
+/* Launch configuration.  Single-precision plans have one coefficient
+ * kernel (blocks of four waves sharing each stage of particles, compensated
+ * folds); double-precision plans have three compiled variants (lanes per
+ * particle in the basis phase).  The grid is one resident round of units
+ * divided by 1, 2, 4 or 8 (fewer, longer units amortise their set-up and
+ * partial rows when n is small).
  * scf_autotune times each (variant, divisor) on the given particles
  * (synchronising the stream) and keeps the fastest for the plan; best_ms
  * (nullable) receives its time.
@@ -462,6 +468,18 @@ typedef struct {
 scf_status scf_profile_enable(scf_plan* plan, int32_t enable);
 scf_status scf_profile_read(scf_plan* plan, scf_kernel_time* out);
 const char* scf_kernel_name(int32_t kind);
+
+/* Issue-rate microbenchmark (measurement only; the ceilings the kernels'
+ * roofline fractions are read against).  kind 0: single-precision FMA chains
+ * (16 independent chains per lane), 1: the same with 32 chains, 2: 4x4x1
+ * (16-block) FP32 MFMA chains, 3: 16x16x4 FP32 MFMA, 4: 32x32x2 FP32 MFMA.
+ * waves_per_simd (1..8) waves share each SIMD (blocks of four waves,
+ * waves_per_simd blocks per compute unit); iters sets the length.  scratch is
+ * a device buffer of at least 4 * waves_per_simd * (compute units) bytes that
+ * the kernel may write.  Returns the achieved TFLOP/s and the kernel time of
+ * the second of two launches on the null stream (blocks). */
+scf_status scf_bench_ceiling(int32_t kind, int32_t waves_per_simd, int32_t iters, void* scratch,
+                             double* tflops, double* ms);
 
 const char* scf_status_string(scf_status status);
 const char* scf_last_error(void);

@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libscf.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["scf_api.cpp", "scf_cadence.cpp", "scf_small.hip", "scf_select.hip", "scf_noalloc.hip",
+           "scf_ceiling.hip",
            "scf_engines_f32_exact.hip", "scf_engines_f32_generic.hip",
            "scf_engines_f64_exact.hip", "scf_engines_f64_generic.hip"]
 HEADERS = ["host_field.h", "scf_device.h", "scf_dual.h", "scf_internal.h", "scf_kernels.h",

@@ -23,10 +23,19 @@
 
 namespace scf {
 
+// Single precision: the hardware reciprocal refined by one Newton step,
+// x1 = x0 + x0 (1 - v x0).  The bare v_rcp_f32 result is off by up to an ulp
+// with a consistent sign over wide ranges of v, which biases cos(theta) = z/r
+// and leaves an isotropic sample with a systematic even-l, m = 0 coefficient
+// of about 1e-8 of a_000; the refined value removes that bias.
 template <typename R>
 __device__ __forceinline__ R d_rcp(R v) {
-  if constexpr (std::is_same<R, float>::value) return __builtin_amdgcn_rcpf(v);
-  else return R(1) / v;
+  if constexpr (std::is_same<R, float>::value) {
+    const float x0 = __builtin_amdgcn_rcpf(v);
+    return fmaf(x0, fmaf(-v, x0, 1.0f), x0);
+  } else {
+    return R(1) / v;
+  }
 }
 template <typename R>
 __device__ __forceinline__ R d_sqrt(R v) { return std::sqrt(v); }

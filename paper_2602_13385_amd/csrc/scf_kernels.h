@@ -1000,6 +1000,429 @@ __global__ void __launch_bounds__(256) hvp_kernel(HvpArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Block coefficient kernel (single precision): the sums of Eq. (sumanlm) with
+// four waves sharing each stage of P particles.
+//   basis phase: one wave (wave k mod 4 at stage k) evaluates, one lane per
+//     particle, xi and the angular-times-mass-radial-prefactor values
+//     v_lj = m G_l Qt_l^m {Re, Im}(u^m) into the particle's LDS record, with
+//     the recurrence constants folded in at compile time;
+//   accumulation phase: every lane of the block owns one tile of NR rows (n)
+//     x 4 columns of one degree l, rebuilds the radial column p_n^(l)(xi) from
+//     p_0 = 1, p_1 = xi, and sweeps its group's share of the stage (group g
+//     takes particles g, g + G, ...), reading its four columns with one
+//     128-bit LDS load;
+//   folds: every FOLD stages (and at the end of the unit) the G groups'
+//     tiles are summed pairwise through LDS and the result is added to the
+//     unit's (hi, lo) pair of partial rows with an error-free two-sum, so the
+//     single-precision sums run over at most FOLD * P / G particles whatever N
+//     is, and the rounding error of each fold is carried in lo.
+// The l-block of a record holds [Re_0, 0, Re_1, Im_1, .., Re_l, Im_l] padded
+// with zeros to a multiple of 4 (so the sine-cosine pairs are 8-byte aligned
+// for 64-bit stores); the record stride PS is a multiple of 4 with PS/4 odd,
+// so the 128-bit tile loads of a wave are free of bank conflicts.
+// ---------------------------------------------------------------------------
+// Order units of the block kernel's basis phase: order 0, order 1, the pairs
+// (2k, 2k+1) for k >= 1, and order lmax alone when it is even and >= 2.  A
+// unit writes whole 4-column chunks of the records (order 0 and order 1 write
+// the two halves of chunk 0), so every record slot is rewritten each stage.
+// The units are assigned to the four waves at compile time, largest first to
+// the least-loaded wave (cost = number of (l, m) values).
+template <int LMAX>
+struct OrderUnits {
+  static constexpr int NPAIR = LMAX >= 3 ? (LMAX - 1) / 2 : 0;          // pairs k = 1..NPAIR
+  static constexpr bool SINGLE = LMAX >= 2 && LMAX % 2 == 0;
+  static constexpr int NU = (LMAX >= 1 ? 2 : 1) + NPAIR + (SINGLE ? 1 : 0);
+  // kind: 0 = order 0, 1 = order 1, 2 = pair (ma, ma + 1), 3 = order ma alone
+  static constexpr int kind(int u) {
+    return u == 0 ? 0 : (LMAX >= 1 && u == 1 ? 1 : (u < NU - (SINGLE ? 1 : 0) ? 2 : 3));
+  }
+  static constexpr int ma(int u) {
+    return kind(u) == 0 ? 0 : kind(u) == 1 ? 1 : kind(u) == 2 ? 2 * (u - 1) : LMAX;
+  }
+  static constexpr int cost(int u) {
+    return kind(u) == 2 ? (LMAX - ma(u) + 1) + (LMAX - ma(u)) : (LMAX - ma(u) + 1);
+  }
+  // wave (of WS sharing a slab of particles) that evaluates unit uq
+  static constexpr int owner(int uq, int WS) {
+    int load[4] = {0, 0, 0, 0};
+    bool done[NU > 0 ? NU : 1] = {};
+    int own = 0;
+    for (int it = 0; it < NU; ++it) {
+      int best = -1;
+      for (int u = 0; u < NU; ++u)
+        if (!done[u] && (best < 0 || cost(u) > cost(best))) best = u;
+      int w = 0;
+      for (int q = 1; q < WS; ++q)
+        if (load[q] < load[w]) w = q;
+      load[w] += cost(best);
+      done[best] = true;
+      if (best == uq) own = w;
+    }
+    return own;
+  }
+};
+
+// u^M (complex) and w^M (real) by squaring, at compile time over M.
+template <int M>
+__device__ __forceinline__ void cpow_u(float ux, float uy, float& er, float& ei) {
+  if constexpr (M == 0) {
+    er = 1.f;
+    ei = 0.f;
+  } else if constexpr (M == 1) {
+    er = ux;
+    ei = uy;
+  } else if constexpr (M % 2 == 0) {
+    float hr, hi;
+    cpow_u<M / 2>(ux, uy, hr, hi);
+    er = hr * hr - hi * hi;
+    ei = 2.f * hr * hi;
+  } else {
+    float hr, hi;
+    cpow_u<M - 1>(ux, uy, hr, hi);
+    er = hr * ux - hi * uy;
+    ei = hr * uy + hi * ux;
+  }
+}
+template <int M>
+__device__ __forceinline__ float rpow(float w) {
+  if constexpr (M == 0) return 1.f;
+  else if constexpr (M == 1) return w;
+  else if constexpr (M % 2 == 0) {
+    const float h = rpow<M / 2>(w);
+    return h * h;
+  } else {
+    return rpow<M - 1>(w) * w;
+  }
+}
+
+// Monic Legendre factor Qt_l^m from the two previous degrees (Qt_m^m = 1,
+// Qt_{m+1}^m = c); order 0, whose even degrees carry a constant term, takes
+// its recurrence constants as float pairs (hi + lo) so that their rounding
+// leaves no bias in an isotropic average.
+template <int L, int M>
+__device__ __forceinline__ float legendre_next(float c, float Q1, float Q0) {
+  if constexpr (L == M) {
+    return 1.f;
+  } else if constexpr (L == M + 1) {
+    return c;
+  } else if constexpr (M == 0) {
+    constexpr double gd = legendre_b(L, M);
+    constexpr float ghi = float(gd);
+    constexpr float glo = float(gd - double(ghi));
+    return fmaf(-glo, Q0, c * Q1 - ghi * Q0);
+  } else {
+    constexpr float gam = float(legendre_b(L, M));
+    return c * Q1 - gam * Q0;
+  }
+}
+
+// The values of one order unit for one particle into its record r:
+// m G_l Qt_l^m {Re, Im}(u^m), with mg0 = m G_0 (zero for a padding particle).
+template <int LMAX, int U, typename AoffF>
+__device__ __forceinline__ void basis_unit(float* r, const Geom<float>& g, float mg0, AoffF aoff) {
+  using OU = OrderUnits<LMAX>;
+  constexpr int K = OU::kind(U), MA = OU::ma(U);
+  float era, eia, erb = 0.f, eib = 0.f;
+  cpow_u<MA>(g.ux, g.uy, era, eia);
+  if constexpr (K == 2) {
+    erb = era * g.ux - eia * g.uy;
+    eib = era * g.uy + eia * g.ux;
+  }
+  float G = mg0 * rpow<MA>(g.w);  // m G_l at l = MA
+  float Qa0 = 0.f, Qa1 = 0.f, Qb0 = 0.f, Qb1 = 0.f;
+  static_for<MA, LMAX + 1>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    const float Qa = legendre_next<l, MA>(g.c, Qa1, Qa0);
+    Qa0 = Qa1;
+    Qa1 = Qa;
+    const float va = Qa * G;
+    float* d = r + aoff(l);
+    if constexpr (K == 0) {
+      if constexpr (l == 0)
+        *reinterpret_cast<float4*>(d) = make_float4(va, 0.f, 0.f, 0.f);
+      else
+        *reinterpret_cast<float2*>(d) = make_float2(va, 0.f);
+    } else if constexpr (K == 1) {
+      *reinterpret_cast<float2*>(d + 2) = make_float2(va * era, va * eia);
+    } else if constexpr (K == 2) {
+      float vb = 0.f;
+      if constexpr (l >= MA + 1) {
+        const float Qb = legendre_next<l, MA + 1>(g.c, Qb1, Qb0);
+        Qb0 = Qb1;
+        Qb1 = Qb;
+        vb = Qb * G;
+      }
+      *reinterpret_cast<float4*>(d + 2 * MA) = make_float4(va * era, va * eia, vb * erb, vb * eib);
+    } else {
+      *reinterpret_cast<float4*>(d + 2 * MA) = make_float4(va * era, va * eia, 0.f, 0.f);
+    }
+    if constexpr (l < LMAX) G *= g.w;
+  });
+}
+
+template <int LMAX, int WS, int W, typename AoffF>
+__device__ __forceinline__ void basis_wave(float* r, const Geom<float>& g, float mg0, AoffF aoff) {
+  using OU = OrderUnits<LMAX>;
+  static_for<0, OU::NU>([&](auto uc) {
+    constexpr int u = decltype(uc)::value;
+    if constexpr (OU::owner(u, WS) == W) basis_unit<LMAX, u>(r, g, mg0, aoff);
+  });
+}
+
+template <int NMAXC, int LMAX>
+struct BlkShape {
+  static constexpr int JT = 4;
+  static constexpr int NR = NMAXC + 1;
+  static constexpr int NT = ntiles_c(LMAX, JT);
+  static constexpr int THREADS = 256;
+  static constexpr int AL = JT * NT;  // angular slots per record
+  static constexpr int XI = AL;       // slot of xi
+  static constexpr int PS = ((AL / 4 + 1) % 2 == 1) ? (AL / 4 + 1) * 4 : (AL / 4 + 2) * 4;
+  // a stage holds SLABS slabs of up to 64 particles (one particle per lane in
+  // the basis phase): the most (1, 2 or 4) whose records fit 39 KB, so that
+  // four blocks share a compute unit's LDS
+  static constexpr int LDS_REC = 39 * 1024 - 4 * (LMAX + 1) * NR;
+  static constexpr int SLABS = (4 * 64 * PS * 4 <= LDS_REC) ? 4 : ((2 * 64 * PS * 4 <= LDS_REC) ? 2 : 1);
+  static constexpr int WS = 4 / SLABS;  // waves sharing a slab (they split its order units)
+  static constexpr int G = (THREADS / NT) > 64 ? 64 : (THREADS / NT);
+  static constexpr int PPG = (64 * SLABS) / G;  // particles per group and stage
+  static constexpr int P = G * PPG;             // particles per stage
+  static constexpr int SLOT = NT * NR * JT;   // floats of one group's tiles
+  static constexpr int NSLOT = (P * PS) / SLOT;  // group tiles the stage buffer holds
+  static constexpr int aoff(int l) { return JT * ntiles_c(l - 1, JT); }
+  static_assert(G >= 1 && NT * G <= THREADS, "tiles must fit the block");
+  static_assert(NSLOT >= 1, "the stage buffer must hold one group's tiles");
+};
+
+// waves per SIMD the block kernel is compiled for: 4 (at most 128 registers)
+// when its tiles have at most 17 rows, else 3
+template <int NMAXC>
+constexpr int blk_waves() { return NMAXC <= 16 ? 4 : 3; }
+
+template <int NMAXC, int LMAX, int FOLD>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(blk_waves<NMAXC>(), blk_waves<NMAXC>())))
+coef_blk_kernel(CoefArgs<float> a) {
+  using S = BlkShape<NMAXC, LMAX>;
+  constexpr int NR = S::NR, NT = S::NT, G = S::G, P = S::P, PS = S::PS, XI = S::XI;
+  constexpr int PPG = S::PPG, SLOT = S::SLOT, NSLOT = S::NSLOT, L2 = (LMAX + 1) * (LMAX + 1);
+  __shared__ __align__(16) float rec[P * PS];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int grp = tid / NT, tau = tid % NT;
+  const bool tv = grp < G;
+  // degree and first column of this lane's tile
+  int tl = 0, tc = 0;
+  {
+    int rem = tau;
+#pragma unroll
+    for (int ll = 0; ll <= LMAX; ++ll) {
+      const int nt = (2 * ll + 1 + 3) / 4;
+      if (rem >= 0 && rem < nt) {
+        tl = ll;
+        tc = 4 * rem;
+      }
+      rem -= nt;
+    }
+  }
+  // radial recurrence constants of every degree, read per stage from LDS so
+  // that they are not live through the basis phase
+  __shared__ __align__(16) float btab[(LMAX + 1) * NR];
+  for (int i = tid; i < (LMAX + 1) * NR; i += 256) btab[i] = a.beta_rad[i];
+
+  // particle range and partial-row pair of this unit
+  const int unit = blockIdx.x;
+  int64_t begin, end;
+  int slot;
+  if (a.seg_begin) {
+    begin = a.seg_begin[unit];
+    end = a.seg_end[unit];
+    slot = a.seg_slot[unit];
+  } else {
+    begin = a.begin + (a.stages * unit / a.nunits) * P;
+    end = a.begin + (a.stages * (unit + 1) / a.nunits) * P;
+    if (end > a.n) end = a.n;
+    slot = unit;
+  }
+  if (begin >= end) return;  // (uniform over the block; launches give every unit a stage)
+
+  // Wave w works on slab w / WS of each stage and evaluates the order units
+  // of rank sub = w mod WS; its lane holds particle q = 64 slab + lane of the
+  // current stage (loaded one stage ahead).  Loads are unconditional, from an
+  // index clamped into the unit's range; pw (0 or 1) removes the particles
+  // past the range.
+  constexpr int WS = S::WS;
+  const int sub = wave % WS, q = (wave / WS) * 64 + lane;
+  float px, py, pz, pm, pw;
+  {
+    const int64_t gi0 = begin + q;
+    const bool ok = q < P && gi0 < end;
+    const int64_t gi = ok ? gi0 : end - 1;
+    px = a.x[gi];
+    py = a.y[gi];
+    pz = a.z[gi];
+    pm = a.m[gi];
+    pw = ok ? 1.f : 0.f;
+  }
+  __syncthreads();
+
+  float acc[NR][4];
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[n][j] = 0.f;
+
+  float* hi = a.partials + (int64_t)slot * 2 * a.T;
+  float* lo = hi + a.T;
+  bool first_fold = true;
+  int k = 0, since = 0;
+  for (int64_t base = begin; base < end; base += P, ++k) {
+    // ---- basis phase: every wave evaluates the geometry of the stage's
+    // particles and the values of its own order units ------------------------
+    if (q < P) {
+      float* r = rec + q * PS;
+      const Geom<float> g = make_geom<float>(px, py, pz, a.binv, a.alpha, a.inv_alpha, a.amode);
+      if (sub == 0) r[XI] = g.xi;
+      const float mg0 = (pm * pw) * g.g0;
+      auto aoff = [](int l) { return S::aoff(l); };
+      if constexpr (WS == 1) {
+        basis_wave<LMAX, 1, 0>(r, g, mg0, aoff);
+      } else if constexpr (WS == 2) {
+        if (sub == 0) basis_wave<LMAX, 2, 0>(r, g, mg0, aoff);
+        else basis_wave<LMAX, 2, 1>(r, g, mg0, aoff);
+      } else {
+        switch (sub) {
+          case 0: basis_wave<LMAX, 4, 0>(r, g, mg0, aoff); break;
+          case 1: basis_wave<LMAX, 4, 1>(r, g, mg0, aoff); break;
+          case 2: basis_wave<LMAX, 4, 2>(r, g, mg0, aoff); break;
+          default: basis_wave<LMAX, 4, 3>(r, g, mg0, aoff); break;
+        }
+      }
+    }
+    {
+      // particle of the next stage; the barriers below wait for LDS traffic
+      // only, so the load stays in flight through the accumulation phase
+      const int64_t gi0 = base + (int64_t)P + q;
+      const bool ok = q < P && gi0 < end;
+      const int64_t gi = ok ? gi0 : end - 1;
+      px = a.x[gi];
+      py = a.y[gi];
+      pz = a.z[gi];
+      pm = a.m[gi];
+      pw = ok ? 1.f : 0.f;
+    }
+    __syncthreads();
+    // ---- accumulation phase -----------------------------------------------
+    if (tv) {
+      float bl[NR];
+#pragma unroll
+      for (int n = 2; n < NR; ++n) bl[n] = btab[tl * NR + n];
+      // operands of the next particle are loaded before this one's FMAs
+      const float* rp = rec + grp * PS;
+      float4 av_n = *reinterpret_cast<const float4*>(rp + 4 * tau);
+      float xi_n = rp[XI];
+#pragma unroll 1
+      for (int ii = 0; ii < PPG; ++ii) {
+        const float4 av = av_n;
+        const float xi = xi_n;
+        if (ii + 1 < PPG) {
+          rp += G * PS;
+          av_n = *reinterpret_cast<const float4*>(rp + 4 * tau);
+          xi_n = rp[XI];
+        }
+        const float a4[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[0][j] += a4[j];
+        if constexpr (NR > 1) {
+          float p0 = 1.f, p1 = xi;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[1][j] = fmaf(p1, a4[j], acc[1][j]);
+#pragma unroll
+          for (int n = 2; n < NR; ++n) {
+            const float p2 = n == 2 ? fmaf(xi, p1, -bl[2]) : fmaf(xi, p1, -bl[n] * p0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[n][j] = fmaf(p2, a4[j], acc[n][j]);
+            p0 = p1;
+            p1 = p2;
+          }
+        }
+      }
+    }
+    ++since;
+    const bool last = base + P >= end;
+    if (since == FOLD || last) {
+      __syncthreads();  // every group has finished reading the stage
+      // ---- groups summed pairwise into group 0 through the stage buffer ----
+      for (int active = G; active > 1;) {
+        const int half = (active + 1) / 2, movers = active - half;
+        for (int c0 = 0; c0 < movers; c0 += NSLOT) {
+          const int c1 = movers < c0 + NSLOT ? movers : c0 + NSLOT;
+          if (tv && grp >= half + c0 && grp < half + c1) {
+            float* d = rec + (grp - half - c0) * SLOT + tau * NR * 4;
+#pragma unroll
+            for (int n = 0; n < NR; ++n)
+              *reinterpret_cast<float4*>(d + 4 * n) =
+                  make_float4(acc[n][0], acc[n][1], acc[n][2], acc[n][3]);
+          }
+          __syncthreads();
+          if (tv && grp >= c0 && grp < c1) {
+            const float* s = rec + (grp - c0) * SLOT + tau * NR * 4;
+#pragma unroll
+            for (int n = 0; n < NR; ++n) {
+              const float4 v = *reinterpret_cast<const float4*>(s + 4 * n);
+              acc[n][0] += v.x;
+              acc[n][1] += v.y;
+              acc[n][2] += v.z;
+              acc[n][3] += v.w;
+            }
+          }
+          __syncthreads();
+        }
+        active = half;
+      }
+      // ---- two-sum fold of the block's sums into the unit's (hi, lo) rows ----
+      // group 0 leaves its tiles in the stage buffer; every thread then folds
+      // coefficients t = tid, tid + 256, .. (coalesced rows)
+      if (tv && grp == 0) {
+        float* d = rec + tau * NR * 4;
+#pragma unroll
+        for (int n = 0; n < NR; ++n)
+          *reinterpret_cast<float4*>(d + 4 * n) =
+              make_float4(acc[n][0], acc[n][1], acc[n][2], acc[n][3]);
+      }
+      __syncthreads();
+      for (int t = tid; t < a.T; t += 256) {
+        const int n = t / L2, lj = t - n * L2;
+        const int l = (int)sqrtf((float)lj + 0.5f), j = lj - l * l;
+        // column of j in the l-block, and the tile holding it
+        const int c = j == 0 ? 0 : j + 1;
+        const int tau_t = (l == 0 ? 0 : l + (l - 1) * (l - 1) / 4) + (c >> 2);
+        const float v = rec[(tau_t * NR + n) * 4 + (c & 3)];
+        if (first_fold) {
+          hi[t] = v;
+          lo[t] = 0.f;
+        } else {
+          const float h = hi[t];
+          const float sum = h + v;
+          const float bp = sum - h;
+          const float err = (h - (sum - bp)) + (v - bp);
+          hi[t] = sum;
+          lo[t] = lo[t] + err;
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < NR; ++n)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[n][j] = 0.f;
+      first_fold = false;
+      since = 0;
+
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // engines
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -1017,16 +1440,24 @@ struct CoefVariants<double> {
   static constexpr int WPB[N] = {1, 1, 1};
 };
 
+// stages per fold of the single-precision block coefficient kernel
+constexpr int kCoefFold = 16;
+
 template <typename R, int NMAXC, int LMAX>
 struct EngineImpl final : Engine {
   using V = CoefVariants<R>;
+  // Single-precision plans have one coefficient kernel, the block kernel with
+  // compensated folds; double-precision plans have the V::N wave-unit variants.
+  static constexpr bool kBlk = sizeof(R) == 4;
+  using BS = BlkShape<NMAXC, LMAX>;
   int nmaxc() const override { return NMAXC; }
   int lmax() const override { return LMAX; }
   int dtype() const override { return sizeof(R) == 4 ? 0 : 1; }
   size_t real_size() const override { return sizeof(R); }
-  int coef_variants() const override { return V::N; }
-  int stage_particles(int v) const override { return 64 / V::LPP[v]; }
+  int coef_variants() const override { return kBlk ? 1 : V::N; }
+  int stage_particles(int v) const override { return kBlk ? BS::P : 64 / V::LPP[v]; }
   int rows_per_unit(int v) const override {
+    if (kBlk) return 2;  // the (hi, lo) pair
     return v == 0 ? rows_t<V::LPP[0]>() : v == 1 ? rows_t<V::LPP[1]>() : rows_t<V::LPP[2]>();
   }
   template <int LPP>
@@ -1037,29 +1468,42 @@ struct EngineImpl final : Engine {
   int max_resident_units(int v) const override {
     int per_cu = 0;
     hipError_t e;
-    if (v == 0)
+    if constexpr (kBlk) {
+      (void)v;
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[0], V::WPB[0]>, 64 * V::WPB[0], 0);
-    else if (v == 1)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[1], V::WPB[1]>, 64 * V::WPB[1], 0);
-    else
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[2], V::WPB[2]>, 64 * V::WPB[2], 0);
-    if (e != hipSuccess || per_cu <= 0) per_cu = 1;
-    return per_cu * V::WPB[v];
+          &per_cu, coef_blk_kernel<NMAXC, LMAX, kCoefFold>, 256, 0);
+      if (e != hipSuccess || per_cu <= 0) per_cu = 1;
+      return per_cu;  // a unit is a block of four waves
+    } else {
+      if (v == 0)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[0], V::WPB[0]>, 64 * V::WPB[0], 0);
+      else if (v == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[1], V::WPB[1]>, 64 * V::WPB[1], 0);
+      else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[2], V::WPB[2]>, 64 * V::WPB[2], 0);
+      if (e != hipSuccess || per_cu <= 0) per_cu = 1;
+      return per_cu * V::WPB[v];
+    }
   }
   hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const override {
     if (nunits <= 0) return hipSuccess;
     const CoefArgs<R>& ca = *(const CoefArgs<R>*)args;
-    const int wpb = V::WPB[v];
-    const int nblocks = (nunits + wpb - 1) / wpb;
-    if (v == 0)
-      coef_kernel<R, NMAXC, LMAX, V::LPP[0], V::WPB[0]><<<nblocks, 64 * V::WPB[0], 0, s>>>(ca);
-    else if (v == 1)
-      coef_kernel<R, NMAXC, LMAX, V::LPP[1], V::WPB[1]><<<nblocks, 64 * V::WPB[1], 0, s>>>(ca);
-    else
-      coef_kernel<R, NMAXC, LMAX, V::LPP[2], V::WPB[2]><<<nblocks, 64 * V::WPB[2], 0, s>>>(ca);
+    if constexpr (kBlk) {
+      (void)v;
+      coef_blk_kernel<NMAXC, LMAX, kCoefFold><<<nunits, 256, 0, s>>>(ca);
+    } else {
+      const int wpb = V::WPB[v];
+      const int nblocks = (nunits + wpb - 1) / wpb;
+      if (v == 0)
+        coef_kernel<R, NMAXC, LMAX, V::LPP[0], V::WPB[0]><<<nblocks, 64 * V::WPB[0], 0, s>>>(ca);
+      else if (v == 1)
+        coef_kernel<R, NMAXC, LMAX, V::LPP[1], V::WPB[1]><<<nblocks, 64 * V::WPB[1], 0, s>>>(ca);
+      else
+        coef_kernel<R, NMAXC, LMAX, V::LPP[2], V::WPB[2]><<<nblocks, 64 * V::WPB[2], 0, s>>>(ca);
+    }
     return hipGetLastError();
   }
   // field variants: 0 and 1 = VALU kernel under two register budgets; 2 and 3
@@ -1151,12 +1595,18 @@ struct EngineImpl final : Engine {
   }
   const char* describe() const override {
     static char buf[200];
-    using S0 = CoefShape<R, NMAXC, LMAX, V::LPP[0]>;
-    using S2 = CoefShape<R, NMAXC, LMAX, V::LPP[2]>;
-    snprintf(buf, sizeof(buf),
-             "%s nmax<=%d lmax=%d coef tiles %dx%d (groups %d|%d, tiles/lane %d|%d)",
-             sizeof(R) == 4 ? "f32" : "f64", NMAXC, LMAX, S0::NR, S0::JT, S0::G, S2::G, S0::KT,
-             S2::KT);
+    if constexpr (kBlk) {
+      snprintf(buf, sizeof(buf),
+               "f32 nmax<=%d lmax=%d coef: block kernel, %d x %d tiles, %d groups, %d particles "
+               "per stage, two-sum folds every %d stages",
+               NMAXC, LMAX, BS::NR, BS::JT, BS::G, BS::P, kCoefFold);
+    } else {
+      using S0 = CoefShape<R, NMAXC, LMAX, V::LPP[0]>;
+      using S2 = CoefShape<R, NMAXC, LMAX, V::LPP[2]>;
+      snprintf(buf, sizeof(buf),
+               "f64 nmax<=%d lmax=%d coef tiles %dx%d (groups %d|%d, tiles/lane %d|%d)", NMAXC,
+               LMAX, S0::NR, S0::JT, S0::G, S2::G, S0::KT, S2::KT);
+    }
     return buf;
   }
 };

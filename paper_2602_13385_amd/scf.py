@@ -173,6 +173,7 @@ SIGNATURES = {
     "scf_profile_enable": (C.c_int, [_vp, C.c_int32]),
     "scf_profile_read": (C.c_int, [_vp, C.c_void_p]),
     "scf_kernel_name": (C.c_char_p, [C.c_int32]),
+    "scf_bench_ceiling": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _vp, _dp, _dp]),
     "scf_status_string": (C.c_char_p, [C.c_int]),
     "scf_last_error": (C.c_char_p, []),
 }
@@ -196,6 +197,19 @@ def lib():
 def _check(status):
     if status != 0:
         raise ScfError(status, lib().scf_last_error().decode())
+
+
+def bench_ceiling(kind, waves_per_simd, iters=20000):
+    """scf_bench_ceiling: (TFLOP/s, ms) of a throughput microbenchmark
+    (kind 0/1: FP32 FMA chains, 2/3/4: FP32 MFMA 4x4x1 / 16x16x4 / 32x32x2)."""
+    torch = _torch()
+    scratch = torch.empty(8 * 4096, dtype=torch.float32, device="cuda")
+    tf = C.c_double()
+    ms = C.c_double()
+    torch.cuda.synchronize()
+    _check(lib().scf_bench_ceiling(int(kind), int(waves_per_simd), int(iters), _ptr(scratch),
+                                   C.byref(tf), C.byref(ms)))
+    return tf.value, ms.value
 
 
 def ncoef(nmax, lmax):

@@ -47,6 +47,25 @@ def coef_err(a, ref):
     return np.abs(a - ref).max() / np.abs(ref).max()
 
 
+FLOOR = {"f32": 2e-8, "f64": 1e-15}
+
+
+def block_errs(a, ref, nmax, lmax, dtype):
+    """Per-l ratio of |da| to TOL * max|a_l-block| + FLOOR * max|a| (<= 1
+    passes); the floor is the absolute resolution single-precision basis
+    evaluation leaves, about 1e-8 |a_000|."""
+    L2 = (lmax + 1) ** 2
+    A = np.asarray(a).reshape(nmax + 1, L2)
+    Rf = np.asarray(ref).reshape(nmax + 1, L2)
+    top = np.abs(Rf).max()
+    out = []
+    for l in range(lmax + 1):
+        sl = slice(l * l, (l + 1) ** 2)
+        out.append(np.abs(A[:, sl] - Rf[:, sl]).max()
+                   / (TOL[dtype] * np.abs(Rf[:, sl]).max() + FLOOR[dtype] * top))
+    return np.array(out)
+
+
 def force_err(g, ref):
     mag = np.sqrt((ref ** 2).sum(0))
     d = np.sqrt(((g - ref) ** 2).sum(0))
@@ -76,6 +95,8 @@ def test_headline_workload_full_size(torch, S, O, dtype):
     torch.cuda.synchronize()
     ref0 = O.coeffs(B, *st0[:3], m)
     assert coef_err(c0.cpu().numpy(), ref0) <= TOL[dtype], coef_err(c0.cpu().numpy(), ref0)
+    be = block_errs(c0.cpu().numpy(), ref0, w.nmax, w.lmax, dtype)
+    assert (be <= 1.0).all(), be
     idx = np.linspace(0, p.n - 1, 2000).astype(int)
     _, a0 = O.field(B, ref0, *st0[:3, idx], pot=False)
     # every field variant at full N (the matrix-core one runs persistent
@@ -102,6 +123,30 @@ def test_headline_workload_full_size(torch, S, O, dtype):
     v1 = v_half + h * a1
     d = np.abs(st1[3:, idx] - v1).max() / np.abs(v1).max()
     assert d <= TOL[dtype], d
+
+
+def test_single_precision_coefficients_at_1e7(torch, S):
+    """Hernquist N = 1e7 (ten times the headline size), nmax 16, lmax 10: the
+    compensated single-precision coefficients against the double-precision
+    GPU path (itself pinned to the oracle above), in the autotuned launch.
+    Each lane's single-precision run is bounded by the fold length, not by N."""
+    n = 10_000_000
+    print(f"[full size] Hernquist N={n} f32 vs f64", flush=True)
+    p = I.hernquist(n, 13385 + 33)
+    pos = p.pos.astype(np.float32)
+    m = p.mass.astype(np.float32)
+    x, y, z = (torch.as_tensor(pos[i], device="cuda") for i in range(3))
+    md = torch.as_tensor(m, device="cuda")
+    p32 = S.Plan(16, 10, dtype="f32")
+    p32.autotune(x, y, z, md)
+    c32 = p32.coeffs(x, y, z, md).cpu().numpy()
+    p64 = S.Plan(16, 10, dtype="f64")
+    c64 = p64.coeffs(x.double(), y.double(), z.double(), md.double()).cpu().numpy()
+    err = coef_err(c32, c64)
+    print(f"  coefficient error {err:.2e}", flush=True)
+    assert err <= TOL["f32"], err
+    be = block_errs(c32, c64, 16, 10, "f32")
+    assert (be <= 1.0).all(), be
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])

@@ -45,6 +45,28 @@ def coef_err(a, ref):
     return np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)
 
 
+# Per degree: |da| <= TOL * max|a_l-block| + FLOOR * max|a|.  Single-precision
+# evaluation of the basis leaves an absolute error of order 1e-8 |a_000| in
+# every coefficient, so a block whose own size is below about 1e-3 |a_000|
+# (the noise-level l > 0 blocks of a near-spherical sample) is resolved only
+# to that floor.
+FLOOR = {"f32": 2e-8, "f64": 1e-15}
+
+
+def block_errs(a, ref, nmax, lmax, dtype):
+    """Per-l ratio of the error to its bound (<= 1 passes)."""
+    L2 = (lmax + 1) ** 2
+    A = np.asarray(a).reshape(nmax + 1, L2)
+    Rf = np.asarray(ref).reshape(nmax + 1, L2)
+    top = np.abs(Rf).max()
+    out = []
+    for l in range(lmax + 1):
+        sl = slice(l * l, (l + 1) ** 2)
+        bound = TOL[dtype] * np.abs(Rf[:, sl]).max() + FLOOR[dtype] * top
+        out.append(np.abs(A[:, sl] - Rf[:, sl]).max() / bound)
+    return np.array(out)
+
+
 def force_err(g, ref):
     mag = np.sqrt((ref ** 2).sum(0))
     d = np.sqrt(((g - ref) ** 2).sum(0))
@@ -94,6 +116,8 @@ def test_coeffs_and_forces_match_oracle(torch, S, O, case, dtype):
         plan.variant = v
         c = _gpu_coeffs(torch, S, plan, pos, m, dtype)
         assert coef_err(c, ref) <= TOL[dtype], (v, coef_err(c, ref))
+        be = block_errs(c, ref, nmax, lmax, dtype)
+        assert (be <= 1.0).all(), (v, be)
     # forces from the reference coefficients, at a sample of the particles
     # (a ragged count), for every field variant
     k = min(n, 2000)
@@ -360,3 +384,72 @@ def test_power_spectrum_matches_oracle(torch, S, O, dtype):
     both = torch.stack([c, 2 * c])
     Eb = plan.power(both).cpu().numpy()
     assert np.allclose(Eb[0], own, rtol=1e-13) and np.allclose(Eb[1], 4 * own, rtol=1e-13)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("alpha", [1.0, 0.8])
+def test_scaled_basis_with_plummer_host(torch, S, O, dtype, alpha):
+    """b != 1 and G != 1 (Eq. psi_nlm with s = r/b; the normalisation scales
+    as b/G), a host with a Plummer and a logarithmic component: coefficients,
+    forces and three KDK steps against the oracle."""
+    b, G = 1.7, 0.6
+    print(f"[parity] scaled basis alpha={alpha} b={b} G={G} {dtype}", flush=True)
+    p = I.plummer(6001, 55, a=1.5, G=G)
+    pos = _rounded(p.pos, dtype)
+    m = _rounded(p.mass, dtype)
+    B = O.basis(10, 6, alpha=alpha, b=b, G=G)
+    ref = O.coeffs(B, *pos, m)
+    plan = S.Plan(10, 6, alpha=alpha, b=b, G=G, dtype=dtype)
+    c = _gpu_coeffs(torch, S, plan, pos, m, dtype)
+    assert coef_err(c, ref) <= TOL[dtype], coef_err(c, ref)
+    assert (block_errs(c, ref, 10, 6, dtype) <= 1.0).all()
+    comps = [("plummer", (40.0, 3.0)), ("log", (1.2, 0.5))]
+    Ho = O.host([(O.HOST_PLUMMER, (40.0, 3.0)), (O.HOST_LOG, (1.2, 0.5))], G=G)
+    centre = np.array([12.0, 5.0, -3.0])
+    _, gscf = O.field(B, ref, *pos)
+    _, g0, _ = O.host_eval(Ho, centre)
+    gh = np.stack([O.host_eval(Ho, centre + pos[:, i])[1] for i in range(pos.shape[1])], axis=1)
+    gref = gscf - gh + g0[:, None]
+    x, y, z = (_dev(torch, pos[i], dtype) for i in range(3))
+    for fv in range(plan.num_field_variants):
+        plan.field_variant = fv
+        ax, ay, az = plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), host=(comps, G),
+                                 centre=centre)
+        torch.cuda.synchronize()
+        g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
+        assert force_err(g, gref) <= TOL[dtype], (fv, force_err(g, gref))
+    cen0 = np.array([12.0, 5.0, -3.0, 0.4, 1.1, -0.2])
+    st0 = _rounded(p.state(), dtype)
+    st_ref, cen_ref, coef_ref, acc_ref = O.step(B, Ho, st0, m, cen0, 0.004, 3, want_acc=True)
+    st = [_dev(torch, st0[i], dtype) for i in range(6)]
+    coef = torch.empty(plan.T, dtype=torch.float64, device="cuda")
+    cen, acc = plan.step(st, _dev(torch, m, dtype), 0.004, 3, host=(comps, G), centre=cen0,
+                         coef_last=coef)
+    torch.cuda.synchronize()
+    out = np.stack([t.cpu().numpy() for t in st]).astype(np.float64)
+    assert np.allclose(cen, cen_ref, rtol=0, atol=1e-12)
+    for rows in (slice(0, 3), slice(3, 6)):
+        d = np.abs(out[rows] - st_ref[rows]).max() / np.abs(st_ref[rows]).max()
+        assert d <= TOL[dtype], d
+    assert coef_err(coef.cpu().numpy(), coef_ref) <= TOL[dtype]
+
+
+def test_single_precision_folds_over_long_unit_ranges(torch, S, O):
+    """With one eighth of a resident round of units, each unit of the
+    single-precision kernel covers about 25 stages at N = 2e5, so its sums
+    pass through more than one two-sum fold into the (hi, lo) rows; the
+    result matches the oracle and the one-round launch."""
+    p = I.hernquist(200_000, 808)
+    pos = _rounded(p.pos, "f32")
+    m = _rounded(p.mass, "f32")
+    B = O.basis(16, 10)
+    ref = O.coeffs(B, *pos, m)
+    plan = S.Plan(16, 10, dtype="f32")
+    outs = []
+    for div in (1, 8):
+        plan.coef_units_div = div
+        outs.append(_gpu_coeffs(torch, S, plan, pos, m, "f32"))
+        assert coef_err(outs[-1], ref) <= TOL["f32"], (div, coef_err(outs[-1], ref))
+        be = block_errs(outs[-1], ref, 16, 10, "f32")
+        assert (be <= 1.0).all(), (div, be)
+    assert coef_err(outs[1], outs[0]) <= TOL["f32"]
