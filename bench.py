@@ -31,8 +31,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak (dense MFMA and vector)
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak (dense MFMA; vector with packed FP32)
 PEAK_FP64_TFLOPS = 78.6
+# The vector ALUs without packed FP32 (which every HIP file here turns off):
+# one wave64 FMA per SIMD per 4 cycles, 256 CUs x 4 SIMDs x 64 lanes x 2 flop
+# / 4 cycles x 2.4 GHz.  The FMA-chain microbenchmark (scf_bench_ceiling)
+# measures 75.6 TFLOP/s at 8 waves per SIMD, 73.0 at 4.
+PEAK_FP32_SINGLE_ISSUE_TFLOPS = 78.6
 METRIC = "particle×basis-term evals/s per step (FP32 vs FP64); adjoint/forward time ratio"
 # The paper's own timings: whole 5 Gyr simulations on other hardware, with its
 # relaxation, refreshes and diagnostics included, so context for the scale of
@@ -62,17 +67,20 @@ def algorithmic_flops(nmax, lmax, host_flops=0):
 
 
 def roofline_entry(kernel, achieved, field_variant, traffic, flops, avg_ms):
-    """The dominant kernel against its ceiling, 157.3 TFLOP/s FP32 either way.
-    The field pass in variants 2 and 3 does its radial sums on the matrix
-    cores (dense FP32 MFMA peak) and the rest on the vector ALUs; the other
-    kernels run on the vector ALUs alone.  Packed FP32 is off, but gfx950
-    still issues plain FP32 FMAs from several waves of a SIMD beyond one wave64
-    instruction per 4 cycles (a chain microbenchmark reached 115 TFLOP/s), so
-    the published vector peak is the vector-ALU ceiling too."""
+    """A kernel against the published FP32 peak, 157.3 TFLOP/s (`frac`).  The
+    field pass in variants 2 and 3 does its radial sums on the matrix cores
+    (dense FP32 MFMA, 157.3) and the rest on the vector ALUs; the other kernels
+    run on the vector ALUs alone, whose published 157.3 counts packed FP32.
+    Packed FP32 is off in every HIP file here, so a vector-ALU kernel's own
+    ceiling is the single-issue 78.6 TFLOP/s (`frac_single_issue_valu`, given
+    for the vector-ALU kernels; measured FMA chains reach 75.6)."""
     mfma = kernel == "field_step" and field_variant >= 2
-    return {"bound": "mfma" if mfma else "alu", "kernel": kernel, "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic, "flops_per_launch": flops, "avg_launch_ms": avg_ms}
+    e = {"bound": "mfma" if mfma else "alu", "kernel": kernel, "achieved": achieved,
+         "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+         "traffic": traffic, "flops_per_launch": flops, "avg_launch_ms": avg_ms}
+    if not mfma:
+        e["frac_single_issue_valu"] = achieved / PEAK_FP32_SINGLE_ISSUE_TFLOPS
+    return e
 
 
 def kernel_source_hash():
@@ -318,10 +326,18 @@ def run_n_scaling(torch, scf, I, sizes=(100_000, 1_000_000, 10_000_000), steps=1
         m = torch.as_tensor(p.mass, dtype=torch.float32, device="cuda")
         plan = scf.Plan(16, 10, dtype="f32")
         plan.autotune(st[0], st[1], st[2], m)
+        # compensated single-precision coefficients against the double-precision
+        # path on the same inputs, before the steps move the particles
+        c32 = plan.coeffs(st[0], st[1], st[2], m).cpu().numpy()
+        p64 = scf.Plan(16, 10, dtype="f64")
+        c64 = p64.coeffs(st[0].double(), st[1].double(), st[2].double(), m.double()).cpu().numpy()
+        cerr = float(np.abs(c32 - c64).max() / np.abs(c64).max())
+        del p64
         cen, acc = plan.step(st, m, 0.005, 2)
         (cen, acc), ms = _timed(torch, lambda: plan.step(st, m, 0.005, steps, centre=cen, acc=acc))
         out.append({"N": n, "ms_per_step": ms / steps, "value": n * plan.T * steps / (ms * 1e-3),
-                    "coef_variant": plan.variant, "field_variant": plan.field_variant})
+                    "coef_variant": plan.variant, "field_variant": plan.field_variant,
+                    "coef_relerr_f32_vs_f64": cerr})
         del st, m, plan, acc
         torch.cuda.empty_cache()
     return {"workload": "hernquist-n16l10 at several N (FP32 step, autotuned)", "steps": steps,
@@ -466,7 +482,72 @@ def run_adjoint(torch, scf, I, nsteps=None):
             "dL_dM_s": float(g[0]), "dL_dr_s": float(g[1]),
             "dL_dcentre0": [float(v) for v in cen0.grad.numpy()],
             "timing": "wall clock around the autograd forward (checkpointed scf_step segments + "
-                      "loss) and backward (scf_step_adjoint per segment, recompute included)"}
+                      "loss) and backward (scf_step_adjoint per segment, recompute included)",
+            "accuracy_vs_horizon": adjoint_horizons(torch, scf, I)}
+
+
+def adjoint_horizons(torch, scf, I, horizons=(100, 500, 1000, 2000), h_rel=1e-5):
+    """The adjoint workload's gradient of the track loss with respect to
+    (M_s, r_s, R0, V0) at several horizons: the FP64 adjoint against FP64
+    central differences of the same loss (step h_rel of the parameter, or of
+    max(1, |coordinate|)), and the FP32 adjoint against the FP64 one,
+    componentwise; escaper set and nearest track points frozen at the FP64
+    base trajectory of each horizon."""
+    import numpy as np
+    from paper_2602_13385_amd import adjoint as A
+    w = I.config5()
+    p = w.clusters[0]
+    ck, track = w.extra["checkpoint"], w.extra["track"]
+    kinds = [w.host[0][0]]
+    theta0 = np.array([list(w.host[0][1])])
+    cen0 = np.array(w.centres[0])
+
+    def setup(dtype):
+        td = torch.float32 if dtype == "f32" else torch.float64
+        return (scf.Plan(w.nmax, w.lmax, dtype=dtype),
+                torch.as_tensor(p.mass, dtype=td, device="cuda"),
+                torch.as_tensor(p.state(), dtype=td, device="cuda").contiguous())
+
+    def grad(plan, m, s0, H, mask, idx):
+        th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+        c = torch.tensor(cen0, dtype=torch.float64, requires_grad=True)
+        sT, cT = A.trajectory(plan, s0.clone(), m, th, c, kinds, w.dt, H, ck)
+        A.track_loss(sT, cT, track, mask, idx).backward()
+        return np.concatenate([th.grad.numpy()[0][:2], c.grad.numpy()]), sT
+
+    (p64, m64, s64), (p32, m32, s32) = setup("f64"), setup("f32")
+    rows = []
+    for H in horizons:
+        with torch.no_grad():
+            sT, cT = A.trajectory(p64, s64, m64, torch.as_tensor(theta0), torch.as_tensor(cen0),
+                                  kinds, w.dt, H, ck)
+            mask = A.escaped_mask(p64, sT, m64)
+            idx = A.nearest_track_points(sT, cT.numpy(), track, mask)
+        g64, sT64 = grad(p64, m64, s64, H, mask, idx)
+
+        def loss(theta, cen):
+            with torch.no_grad():
+                a, b = A.trajectory(p64, s64, m64, torch.as_tensor(theta), torch.as_tensor(cen),
+                                    kinds, w.dt, H, ck)
+                return float(A.track_loss(a, b, track, mask, idx).item())
+        fd = np.zeros(8)
+        for q in range(8):
+            th, c = theta0.copy(), cen0.copy()
+            arr, k = (th[0], q) if q < 2 else (c, q - 2)
+            h = h_rel * (abs(arr[k]) if q < 2 else max(1.0, abs(arr[k])))
+            arr[k] += h
+            lp = loss(th, c)
+            arr[k] -= 2 * h
+            fd[q] = (lp - loss(th, c)) / (2 * h)
+        g32, sT32 = grad(p32, m32, s32, H, mask, idx)
+        rows.append({"steps": H, "escapers": int(mask.sum().item()),
+                     "grad_f64": [float(v) for v in g64],
+                     "relerr_f64_adjoint_vs_f64_fd": [float(v) for v in np.abs(g64 - fd) / np.abs(g64)],
+                     "relerr_f32_vs_f64_adjoint": [float(v) for v in np.abs(g32 - g64) / np.abs(g64)],
+                     "forward_pos_relerr_f32_vs_f64": float(
+                         ((sT32[:3].double() - sT64[:3]).abs().max() / sT64[:3].abs().max()).item())})
+    return {"parameters": ["M_s", "r_s", "X0", "Y0", "Z0", "VX0", "VY0", "VZ0"],
+            "fd_step": h_rel, "horizons": rows}
 
 
 def run_diagnostics(torch, scf, I, chunks=10, per_chunk=200):
@@ -496,6 +577,20 @@ def run_diagnostics(torch, scf, I, chunks=10, per_chunk=200):
             "t": [r["t"] for r in rows], "R": [r["R"] for r in rows],
             "E_l_over_initial": [[e / e0 for e, e0 in zip(r["E_l"], E0)] for r in rows],
             "tidal_norm_over_initial": [r["tidal_norm"] / T0 for r in rows]}
+
+
+def run_ceilings(scf):
+    """Issue-rate ceilings (scf_bench_ceiling): single-precision FMA chains
+    without packed FP32, and FP32 MFMA chains, at 1, 2, 4 and 8 waves per
+    SIMD, in TFLOP/s."""
+    names = {0: "fma_f32_16_chains", 1: "fma_f32_32_chains", 2: "mfma_f32_4x4x1",
+             3: "mfma_f32_16x16x4", 4: "mfma_f32_32x32x2"}
+    out = {}
+    for kind, name in names.items():
+        out[name] = {str(wv): scf.bench_ceiling(kind, wv, 4000 if kind < 2 else 2000)[0]
+                     for wv in (1, 2, 4, 8)}
+    out["note"] = "waves per SIMD -> TFLOP/s; the kernels' roofline fractions are read against these"
+    return out
 
 
 def device_info(torch):
@@ -563,7 +658,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (f64, accuracy, batched, adjoint, long, "
-                         "diagnostics, cadence, nscaling) or 'all'")
+                         "diagnostics, cadence, nscaling, ceilings) or 'all'")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline FP32 workload only (no FP64, batched, adjoint, accuracy)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -609,6 +704,8 @@ def main():
             e = roofline_entry(k, tf, r["field_variant"], None, fl[k] * n, tot / cnt)
             per_kernel[k] = {"avg_launch_ms": tot / cnt, "tflops": tf, "bound": e["bound"],
                              "frac": e["frac"]}
+            if "frac_single_issue_valu" in e:
+                per_kernel[k]["frac_single_issue_valu"] = e["frac_single_issue_valu"]
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_launch_ms"])
     achieved = per_kernel[dom]["tflops"]
     step_tf = (fl["coef"] + fl["field_step"]) * n / (ms_per_step * 1e-3) / 1e12
@@ -637,7 +734,7 @@ def main():
     }
     del r["plan"]
     legs = set(("f64", "accuracy", "batched", "adjoint", "long", "diagnostics", "cadence",
-                "nscaling")
+                "nscaling", "ceilings")
                if args.legs == "all" else args.legs.split(","))
     if args.no_f64:
         legs.discard("f64")
@@ -653,7 +750,8 @@ def main():
                           "f32_over_f64_speed": (r64["ms"] / steps64) / ms_per_step}
             del r64["plan"]
         legs_fn = [("accuracy", "accuracy", lambda: accuracy_main(torch, scf, I)),
-                   ("batched", "batched", lambda: run_batched(torch, scf, I, steps=50)),
+                   ("batched", "batched", lambda: run_batched(torch, scf, I, steps=1000)),
+                   ("ceilings", "throughput ceilings", lambda: run_ceilings(scf)),
                    ("adjoint", "adjoint", lambda: run_adjoint(torch, scf, I)),
                    ("long", "long runs", lambda: run_long(torch, scf, I)),
                    ("diagnostics", "diagnostics", lambda: run_diagnostics(torch, scf, I)),

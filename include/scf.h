@@ -276,6 +276,13 @@ typedef struct {
   double alpha_min;       /* lower bound of alpha for retune, in (0, 1) */
 } scf_cadence;
 
+/* The paper's cadence parameters (Sec. 2.2): eta = 1/400, dt_max = 0.005,
+ * frac = 0.999, a complete refresh every fifth interval, one orbit sample per
+ * t_dyn with c_dyn restating t_dyn = 4.3451 Myr at 1e5 Msun and 10 pc
+ * (2.91430...), at most 8 samples per interval, no recentring or retuning,
+ * alpha_min = 0.25. */
+void scf_cadence_defaults(scf_cadence* cadence);
+
 /* Cadence state carried between calls (host, in/out). */
 typedef struct {
   int32_t since;  /* intervals since the last complete refresh */

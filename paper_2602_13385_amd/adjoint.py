@@ -71,14 +71,11 @@ def trajectory(plan, state0, m, theta, centre0, kinds, dt, nsteps, checkpoint=10
                                checkpoint)
 
 
-def escaped_mask(plan, state, m, host=None, centre=None):
-    """Escapers in the cluster frame: 1/2 |v|^2 + psi_SCF(x) >= 0 (not differentiated)."""
+def escaped_mask(plan, state, m):
+    """Escapers in the cluster frame, 1/2 |v|^2 + psi_SCF(x) >= 0 (not
+    differentiated): the library's bound test (scf_select)."""
     with torch.no_grad():
-        x, y, z, vx, vy, vz = (state[i].contiguous() for i in range(6))
-        coef = plan.coeffs(x, y, z, m)
-        _, _, _, pot = plan.forces(x, y, z, coef, pot=True)
-        e = 0.5 * (vx * vx + vy * vy + vz * vz) + pot
-        return e >= 0
+        return plan.escaped([state[i].contiguous() for i in range(6)], m)
 
 
 def nearest_track_points(state, centre, track, mask):

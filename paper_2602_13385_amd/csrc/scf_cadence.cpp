@@ -445,6 +445,26 @@ scf_status set_basis_impl(scf_plan* p, double alpha, double b) {
 
 extern "C" {
 
+void scf_cadence_defaults(scf_cadence* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->eta = 1.0 / 400.0;  // Eq. (tidal_timestep)
+  c->dt_max = 0.005;
+  c->frac = 0.999;       // r_99.9
+  // t_dyn = 4.3451 Myr at M = 1e5 Msun and r = 10 pc, written as
+  // c_dyn sqrt(r^3 / (G M)): with G = 4.30091727e-3 pc (km/s)^2 / Msun the
+  // square root is sqrt(1000 / 430.091727) pc/(km/s), and 1 pc/(km/s) is
+  // 3.0856775814913673e13 km / 3.15576e13 s-per-Myr = 0.977792 Myr
+  c->c_dyn = 4.3451 / (std::sqrt(1000.0 / (4.30091727e-3 * 1e5)) *
+                       (3.0856775814913673e13 / 3.15576e13));
+  c->refresh_every = 5;
+  c->n_samples_tdyn = 1;
+  c->ns_max = 8;
+  c->recentre = 0;
+  c->retune = 0;
+  c->alpha_min = 0.25;
+}
+
 scf_status scf_cadence_workspace_size(const scf_plan* p, int64_t n, int32_t ns_max, size_t* bytes) {
   if (!p || !bytes) return fail(SCF_ERR_INVALID_ARG, "plan and bytes must be non-null");
   if (n < 0) return fail(SCF_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);

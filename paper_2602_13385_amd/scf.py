@@ -75,27 +75,33 @@ class CIntervalLog(C.Structure):
 
 
 MAX_SAMPLES = 16
-# t_dyn = C_DYN sqrt(r_hm^3 / (G M)): the paper's 4.3451 Myr at 1e5 Msun and
-# 10 pc, with G = 4.30091727e-3 pc (km/s)^2 / Msun and 1 pc/(km/s) = 0.977792 Myr
-C_DYN = 4.3451 / ((1000.0 / (4.30091727e-3 * 1e5)) ** 0.5 * (3.0856775814913673e13 / 3.15576e13))
+
+
+def paper_c_dyn():
+    """c_dyn of the paper's t_dyn (scf_cadence_defaults)."""
+    c = CCadence()
+    lib().scf_cadence_defaults(C.byref(c))
+    return c.c_dyn
 
 
 @dataclass
 class Cadence:
-    """Parameters of the refresh cadence (include/scf.h, scf_cadence)."""
+    """Parameters of the refresh cadence (include/scf.h, scf_cadence); c_dyn =
+    None takes the library's value of the paper's t_dyn."""
     eta: float = 1.0 / 400.0
     dt_max: float = 0.005
     frac: float = 0.999
     refresh_every: int = 5
     n_samples_tdyn: int = 0
-    c_dyn: float = C_DYN
+    c_dyn: float = None
     ns_max: int = 8
     recentre: bool = False
     retune: bool = False
     alpha_min: float = 0.25
 
     def c(self):
-        return CCadence(float(self.eta), float(self.dt_max), float(self.frac), float(self.c_dyn),
+        c_dyn = paper_c_dyn() if self.c_dyn is None else self.c_dyn
+        return CCadence(float(self.eta), float(self.dt_max), float(self.frac), float(c_dyn),
                         int(self.refresh_every), int(self.n_samples_tdyn), int(self.ns_max),
                         1 if self.recentre else 0, 1 if self.retune else 0, 0,
                         float(self.alpha_min))
@@ -147,6 +153,7 @@ SIGNATURES = {
                                      C.c_size_t, _vp, _dp]),
     "scf_power_spectrum": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "scf_tidal_norm": (C.c_int, [C.POINTER(CHost), _dp, _dp]),
+    "scf_cadence_defaults": (None, [C.c_void_p]),
     "scf_cadence_workspace_size": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
     "scf_step_frozen": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   C.c_uint32, _vp, C.POINTER(CHost), _dp, C.c_double, C.c_int32,
@@ -548,6 +555,14 @@ class Plan:
         d = _state_dict(out)
         del d["since"]
         return w, b, d
+
+    def escaped(self, st, m):
+        """Escapers of st in the potential of the particles' own coefficients
+        (|v|^2/2 + psi_SCF >= 0, cluster frame): the complement of
+        scf_select's bound flags, as a device bool tensor."""
+        coef = self.coeffs(st[0], st[1], st[2], m)
+        _, b, _ = self.select([t.contiguous() for t in st], m, coef, 1.0, bound=True)
+        return b == 0
 
     def coeffs_delta(self, snaps, w_old, w_new, coef):
         """coef += mean over snapshots [(x, y, z), ...] of the coefficients of

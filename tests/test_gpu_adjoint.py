@@ -166,3 +166,71 @@ def test_autograd_checkpoints_match_finite_differences(torch, S):
                 return float((w * sT).sum() + (c * cT).sum())
             fd = (Ls(sp) - Ls(sm)) / (2 * h)
             assert abs(fd - g_s0[row, i]) <= 1e-5 * max(abs(g_s0[row, i]), 1e-3), (row, i, fd)
+
+
+def test_track_loss_gradient_over_full_horizon(torch, S):
+    """The adjoint workload at its own size and horizon (Plummer N = 1e5, NFW
+    host, 2000 steps of 0.005, checkpoints every 100): the FP64 adjoint
+    gradient of the track loss with respect to (M_s, r_s, R0, V0) against
+    FP64 central differences of the same loss (escaper set and nearest track
+    points frozen at the FP64 base trajectory), and the FP32 adjoint against
+    the FP64 one at the 1e-3 gradient bar, componentwise."""
+    from paper_2602_13385_amd import adjoint as A
+    w = I.config5()
+    p = w.clusters[0]
+    H, ck = w.nsteps, w.extra["checkpoint"]
+    kinds = [w.host[0][0]]
+    theta0 = np.array([list(w.host[0][1])])
+    cen0 = np.array(w.centres[0])
+    track = w.extra["track"]
+
+    def setup(dtype):
+        td = torch.float32 if dtype == "f32" else torch.float64
+        return (S.Plan(w.nmax, w.lmax, dtype=dtype), torch.as_tensor(p.mass, dtype=td, device="cuda"),
+                torch.as_tensor(p.state(), dtype=td, device="cuda").contiguous())
+
+    def grad(plan, m, s0, mask, idx):
+        th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+        c = torch.tensor(cen0, dtype=torch.float64, requires_grad=True)
+        sT, cT = A.trajectory(plan, s0.clone(), m, th, c, kinds, w.dt, H, ck)
+        A.track_loss(sT, cT, track, mask, idx).backward()
+        return np.concatenate([th.grad.numpy()[0][:2], c.grad.numpy()])
+
+    plan, m, s0 = setup("f64")
+    print(f"[adjoint horizon] N={p.n} steps={H}", flush=True)
+    with torch.no_grad():
+        sT, cT = A.trajectory(plan, s0, m, torch.as_tensor(theta0), torch.as_tensor(cen0), kinds,
+                              w.dt, H, ck)
+        mask = plan.escaped(sT, m)
+        idx = A.nearest_track_points(sT, cT.numpy(), track, mask)
+    assert int(mask.sum()) > 100
+    g64 = grad(plan, m, s0, mask, idx)
+
+    def loss(theta, cen):
+        with torch.no_grad():
+            sT, cT = A.trajectory(plan, s0, m, torch.as_tensor(theta), torch.as_tensor(cen), kinds,
+                                  w.dt, H, ck)
+            return float(A.track_loss(sT, cT, track, mask, idx).item())
+
+    fd = np.zeros(8)
+    for q in range(8):
+        th, c = theta0.copy(), cen0.copy()
+        if q < 2:
+            h = 1e-5 * abs(th[0, q])
+            th[0, q] += h
+            lp = loss(th, c)
+            th[0, q] -= 2 * h
+            lm = loss(th, c)
+        else:
+            h = 1e-5 * max(1.0, abs(c[q - 2]))
+            c[q - 2] += h
+            lp = loss(th, c)
+            c[q - 2] -= 2 * h
+            lm = loss(th, c)
+        fd[q] = (lp - lm) / (2 * h)
+    assert (np.abs(g64 - fd) <= 1e-5 * np.abs(g64)).all(), (g64, fd)
+    plan32, m32, s032 = setup("f32")
+    g32 = grad(plan32, m32, s032, mask, idx)
+    rel = np.abs(g32 - g64) / np.abs(g64)
+    print(f"  FP32 vs FP64 gradient, componentwise max {rel.max():.1e}", flush=True)
+    assert (rel <= 1e-3).all(), rel
