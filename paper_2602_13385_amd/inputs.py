@@ -13,6 +13,7 @@ Units: G = M = a = 1 (N-body units) unless stated otherwise.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -193,22 +194,31 @@ CONFIG4_HOST = [("hernquist", (1.11955, 1.0, 0.0)),
                 ("nfw", (124.107, 15.626, 0.0))]
 
 
-def _flat_curve_apocentre_speed(r_apo: float, e: float, vc: float = 1.5) -> float:
-    """Tangential speed at apocentre for eccentricity e in a flat rotation
-    curve (psi = vc^2 ln r): energy and angular-momentum conservation between
-    apo- and pericentre give v_a^2 = 2 vc^2 ln(r_a/r_p) / (r_a^2/r_p^2 - 1)."""
-    r_p = r_apo * (1.0 - e) / (1.0 + e)
-    ratio = r_apo / r_p
-    return vc * math.sqrt(2.0 * math.log(ratio) / (ratio * ratio - 1.0))
+BATCHED_ORBITS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                              "tests", "golden", "batched_orbits.txt")
 
 
-def config4(nclust: int = 10, nmin: float = 2e4, nmax_n: float = 5e5) -> Workload:
-    """10 Plummer progenitors, N log-uniform in [2e4, 5e5], eccentric orbits."""
+def batched_orbit_speeds(path: str = BATCHED_ORBITS) -> np.ndarray:
+    """Apocentre speeds of the batched workload's orbits: a stored table (the
+    speeds whose orbits, integrated in the composite host, have the drawn
+    eccentricities; written once by tests/golden/make_batched_orbits.py)."""
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return np.array([float(r[3]) for r in rows])
+
+
+def config4(nclust: int = 10, nmin: float = 2e4, nmax_n: float = 5e5,
+            orbit_speeds="stored") -> Workload:
+    """10 Plummer progenitors, N log-uniform in [2e4, 5e5], eccentric orbits:
+    e ~ U(0.1, 0.7) and r_apo ~ U(15, 40), an isotropic orbital plane, the
+    start at apocentre with the tangential speed of the stored table
+    (orbit_speeds=None leaves the speeds zero, for the script that finds them)."""
     rng = _rng(SEED_BASE + 4)
     ns = np.round(np.exp(rng.uniform(math.log(nmin), math.log(nmax_n), nclust))).astype(int)
     es = rng.uniform(0.1, 0.7, nclust)
     rapo = rng.uniform(15.0, 40.0, nclust)
-    clusters, centres = [], []
+    speeds = batched_orbit_speeds() if orbit_speeds == "stored" else np.zeros(nclust)
+    assert len(speeds) == nclust
+    clusters, centres, planes = [], [], []
     for i in range(nclust):
         clusters.append(plummer(int(ns[i]), SEED_BASE + 400 + i))
         nrm = _isotropic(rng, 1)[:, 0]  # orbital-plane normal
@@ -217,10 +227,11 @@ def config4(nclust: int = 10, nmin: float = 2e4, nmax_n: float = 5e5) -> Workloa
         e1 = np.cross(nrm, tmp)
         e1 /= np.linalg.norm(e1)
         e2 = np.cross(nrm, e1)
-        v = _flat_curve_apocentre_speed(rapo[i], es[i])
-        centres.append(np.concatenate([rapo[i] * e1, v * e2]))
+        planes.append((e1, e2))
+        centres.append(np.concatenate([rapo[i] * e1, speeds[i] * e2]))
     return Workload("batched-10-plummer-n10l6-composite-host", 10, 6, 0.005, 1000, clusters,
-                    centres, list(CONFIG4_HOST), extra={"e_target": es, "r_apo": rapo})
+                    centres, list(CONFIG4_HOST),
+                    extra={"e_target": es, "r_apo": rapo, "plane": planes})
 
 
 def config5(n: int = 100_000) -> Workload:

@@ -54,8 +54,7 @@ def _clusters(sizes, seed):
         p = I.plummer(max(n, 1), seed + 10 + i)
         parts.append(p.state()[:, :n])
         r_apo = rng.uniform(15.0, 40.0)
-        e = rng.uniform(0.1, 0.7)
-        v = I._flat_curve_apocentre_speed(r_apo, e)
+        v = rng.uniform(0.5, 1.3)  # tangential: an eccentric bound orbit in this host
         th = rng.uniform(0, 2 * math.pi)
         cens.append(np.array([r_apo * math.cos(th), r_apo * math.sin(th), 0.3,
                               -v * math.sin(th), v * math.cos(th), 0.05]))
