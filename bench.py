@@ -590,6 +590,17 @@ def run_ceilings(scf):
         out[name] = {str(wv): scf.bench_ceiling(kind, wv, 4000 if kind < 2 else 2000)[0]
                      for wv in (1, 2, 4, 8)}
     out["note"] = "waves per SIMD -> TFLOP/s; the kernels' roofline fractions are read against these"
+    # overlap check: kinds 0 and 2 together in every wave against the sum of
+    # their separate times (same iters and waves)
+    ov = {}
+    for wv in (2, 4, 8):
+        t_fma = scf.bench_ceiling(0, wv, 4000)[1]
+        t_mfma = scf.bench_ceiling(2, wv, 4000)[1]
+        t_mix = scf.bench_ceiling(5, wv, 4000)[1]
+        ov[str(wv)] = {"fma_ms": t_fma, "mfma_ms": t_mfma, "both_ms": t_mix,
+                       "both_over_sum": t_mix / (t_fma + t_mfma),
+                       "both_over_max": t_mix / max(t_fma, t_mfma)}
+    out["fma_mfma_overlap"] = ov
     return out
 
 

@@ -479,8 +479,10 @@ const char* scf_kernel_name(int32_t kind);
 /* Issue-rate microbenchmark (measurement only; the ceilings the kernels'
  * roofline fractions are read against).  kind 0: single-precision FMA chains
  * (16 independent chains per lane), 1: the same with 32 chains, 2: 4x4x1
- * (16-block) FP32 MFMA chains, 3: 16x16x4 FP32 MFMA, 4: 32x32x2 FP32 MFMA.
- * waves_per_simd (1..8) waves share each SIMD (blocks of four waves,
+ * (16-block) FP32 MFMA chains, 3: 16x16x4 FP32 MFMA, 4: 32x32x2 FP32 MFMA,
+ * 5: the work of kinds 0 and 2 (at the same iters) in every wave, as
+ * independent chains (its time against the sum of theirs shows whether the
+ * vector ALU and the matrix core overlap).  waves_per_simd (1..8) waves share each SIMD (blocks of four waves,
  * waves_per_simd blocks per compute unit); iters sets the length.  scratch is
  * a device buffer of at least 4 * waves_per_simd * (compute units) bytes that
  * the kernel may write.  Returns the achieved TFLOP/s and the kernel time of

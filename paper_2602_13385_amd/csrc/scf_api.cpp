@@ -447,8 +447,11 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
       if (st != SCF_OK) return st;
       // closing half kick of step k merged with the opening half kick of
       // step k+1, then the drift of step k+1
-      st = run_field<Rt>(p, n, x, y, z, vx, vy, vz, ax, ay, az, nullptr, W, hp, row, 1,
-                         last ? h : dt, last ? 0.0 : dt, s);
+      // (the accelerations are stored on the last step only: the merged
+      // kicks of the other steps do not read them back)
+      st = run_field<Rt>(p, n, x, y, z, vx, vy, vz, last ? ax : nullptr, last ? ay : nullptr,
+                         last ? az : nullptr, nullptr, W, hp, row, 1, last ? h : dt,
+                         last ? 0.0 : dt, s);
       if (st != SCF_OK) return st;
       centre_accel(hd, R, gc);
       for (int i = 0; i < 3; ++i) V[i] += (last ? h : dt) * gc[i];
@@ -503,7 +506,6 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
   // ---- work lists (host), staged in pinned memory --------------------------
   const int v = p->coef_variant;
   const int P = p->eng->stage_particles(v);
-  const int rpu = p->eng->rows_per_unit(v);
   const int cap = std::max(1, p->resident[v] * p->num_cu);
   std::vector<int64_t> stg(ncl);
   int64_t st_tot = 0;
@@ -512,10 +514,11 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
     st_tot += stg[c];
   }
   std::vector<int64_t> sb, se;
-  std::vector<int32_t> slot, rows(ncl + 1, 0), bcl;
+  std::vector<int32_t> slot, unit_start(ncl + 1, 0), rows(ncl + 1, 0), bcl;
   std::vector<int64_t> bb, be;
+  int64_t max_stages = 0;
   for (int c = 0; c < ncl; ++c) {
-    rows[c] = (int32_t)(sb.size() * rpu);
+    unit_start[c] = (int32_t)sb.size();
     if (stg[c] == 0) continue;
     int64_t uc = (int64_t)((double)cap * (double)stg[c] / (double)st_tot);
     uc = std::max<int64_t>(1, std::min<int64_t>(uc, stg[c]));
@@ -524,9 +527,13 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
       sb.push_back(offsets[c] + s0 * P);
       se.push_back(std::min(offsets[c] + s1 * P, offsets[c + 1]));
       slot.push_back((int32_t)slot.size());
+      max_stages = std::max(max_stages, s1 - s0);
     }
   }
-  rows[ncl] = (int32_t)(sb.size() * rpu);
+  unit_start[ncl] = (int32_t)sb.size();
+  // partial rows of cluster c: [rows[c], rows[c+1])
+  const int rpu = unit_rows(p, v, max_stages);
+  for (int c = 0; c <= ncl; ++c) rows[c] = unit_start[c] * rpu;
   for (int c = 0; c < ncl; ++c)
     for (int64_t b0 = offsets[c]; b0 < offsets[c + 1]; b0 += 256) {
       bcl.push_back(c);
@@ -636,6 +643,11 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
   };
 
   const int nch = std::max(1, std::min(kReduceChunks, rows[ncl] > 0 ? (rows[ncl] + ncl - 1) / ncl : 1));
+  // one reduction launch when no cluster has more partial rows than the
+  // single-pass kernel takes
+  int max_cluster_rows = 0;
+  for (int c = 0; c < ncl; ++c) max_cluster_rows = std::max(max_cluster_rows, rows[c + 1] - rows[c]);
+  const bool one_pass = max_cluster_rows <= kSmallRows;
   const int64_t W_stride = (int64_t)(p->nmaxc + 1) * (p->lmax + 1) * (p->lmax + 1);
   double* coef_int = (double*)(w + B.L.coef);
   void* Wb = w + B.L.W;
@@ -656,6 +668,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
     ca.n = n;
     ca.nunits = U;
     ca.partials = (Rt*)(w + B.L.partials);
+    ca.one_row = rpu == 1;
     ForceArgs<Rt> fa;
     fill_force_common(fa, p);
     fa.x = (Rt*)x;
@@ -681,20 +694,29 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
     // one step's kernels: coefficients of every cluster, their reduction and
     // finalisation (which also selects this step's centre rows), then the
     // fused field + kick (+ drift) pass
-    auto enqueue = [&](hipStream_t q, double kick, double drift, double* coef) -> scf_status {
+    auto enqueue = [&](hipStream_t q, double kick, double drift, double* coef,
+                       bool store_acc) -> scf_status {
       {
         Timed t(p, q, K_BATCH_COEF);
         HIP_TRY(p->eng->launch_coef(&ca, U, v, q));
       }
-      HIP_TRY(launch_reduce_batched(p->dtype, ca.partials, (const int32_t*)(w + B.rows), ncl,
-                                    (int)p->T, nch, (double*)(w + B.L.red1), q));
-      HIP_TRY(launch_finalize_batched(p->dtype, (const double*)(w + B.L.red1), nch, (int)p->T,
-                                      p->nmax, p->lmax, p->nmaxc, p->d_cs, p->d_fw, coef, Wb,
-                                      W_stride, (const double*)(w + B.tab), ncl,
-                                      (double*)(w + B.cur), (int*)(w + B.ctr), q));
+      if (one_pass) {
+        HIP_TRY(launch_reduce_final_batched(p->dtype, ca.partials, (const int32_t*)(w + B.rows),
+                                            ncl, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
+                                            p->d_fw, coef, Wb, W_stride, (const double*)(w + B.tab),
+                                            (double*)(w + B.cur), (int*)(w + B.ctr), q));
+      } else {
+        HIP_TRY(launch_reduce_batched(p->dtype, ca.partials, (const int32_t*)(w + B.rows), ncl,
+                                      (int)p->T, nch, (double*)(w + B.L.red1), q));
+        HIP_TRY(launch_finalize_batched(p->dtype, (const double*)(w + B.L.red1), nch, (int)p->T,
+                                        p->nmax, p->lmax, p->nmaxc, p->d_cs, p->d_fw, coef, Wb,
+                                        W_stride, (const double*)(w + B.tab), ncl,
+                                        (double*)(w + B.cur), (int*)(w + B.ctr), q));
+      }
       ForceArgs<Rt> f2 = fa;
       f2.kick = Rt(kick);
       f2.drift = Rt(drift);
+      if (!store_acc) f2.ax = f2.ay = f2.az = nullptr;
       HIP_TRY(p->eng->launch_force(&f2, nblk, 1, p->field_variant, q));
       return SCF_OK;
     };
@@ -703,7 +725,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
     int64_t chunk0 = acc_valid ? 1 : 0;
     if (!acc_valid) {
       // a(x0): field pass with no kick and no drift (v is rewritten unchanged)
-      st = enqueue(s, 0.0, 0.0, nsteps == 0 && coef_last ? coef_last : coef_int);
+      st = enqueue(s, 0.0, 0.0, nsteps == 0 && coef_last ? coef_last : coef_int, true);
       if (st != SCF_OK) return st;
     }
     if (nsteps == 0) return SCF_OK;
@@ -724,6 +746,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
       add(&U, sizeof(U));
       add(&nblk, sizeof(nblk));
       add(&nch, sizeof(nch));
+      add(&one_pass, sizeof(one_pass));
       add(&v, sizeof(v));
       add(&p->field_variant, sizeof(p->field_variant));
       add(&coef_int, sizeof(coef_int));
@@ -743,7 +766,7 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
         for (int rep : {1, kGraphSteps}) {
           HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
           scf_status cs = SCF_OK;
-          for (int r = 0; r < rep && cs == SCF_OK; ++r) cs = enqueue(p->cap_stream, dt, dt, coef_int);
+          for (int r = 0; r < rep && cs == SCF_OK; ++r) cs = enqueue(p->cap_stream, dt, dt, coef_int, false);
           hipGraph_t g = nullptr;
           hipError_t ee = hipStreamEndCapture(p->cap_stream, &g);
           if (cs != SCF_OK) {
@@ -789,7 +812,8 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
         Timed t(p, s, K_BATCH_FIELD);
         HIP_TRY(hipGraphLaunch(p->gexec, s));
       } else {
-        st = enqueue(s, last ? h : dt, last ? 0.0 : dt, last && coef_last ? coef_last : coef_int);
+        st = enqueue(s, last ? h : dt, last ? 0.0 : dt, last && coef_last ? coef_last : coef_int,
+                     last);
         if (st != SCF_OK) return st;
       }
       ++k;

@@ -73,6 +73,32 @@ __global__ void __launch_bounds__(256) mfma_chains_kernel(float* out, int iters,
   }
 }
 
+// Both in one wave: per step four 4x4x1 MFMA chains and 16 FMA chains,
+// independent of each other (the same per-wave counts as kinds 0 and 2 at the
+// same iters), so that a pipe able to overlap them would finish in the time
+// of the longer of the two.
+__global__ void __launch_bounds__(256) mixed_chains_kernel(float* out, int iters, float a, float b) {
+  float acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = float(threadIdx.x + i);
+  mf4 c0 = {0, 0, 0, 0}, c1 = c0, c2 = c0, c3 = c0;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      c0 = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c3, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = fmaf(acc[i], a, b);
+    }
+  }
+  float s = c0[0] + c1[1] + c2[2] + c3[3];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s += acc[i];
+  if (s == 1234.5f) out[blockIdx.x] = s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -80,7 +106,7 @@ extern "C" {
 scf_status scf_bench_ceiling(int32_t kind, int32_t waves_per_simd, int32_t iters, void* scratch,
                              double* tflops, double* ms) {
   if (!tflops || !ms || !scratch) return fail(SCF_ERR_INVALID_ARG, "null argument");
-  if (kind < 0 || kind > 4 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1)
+  if (kind < 0 || kind > 5 || waves_per_simd < 1 || waves_per_simd > 8 || iters < 1)
     return fail(SCF_ERR_INVALID_ARG, "bad kind, waves_per_simd or iters");
   int dev = 0, ncu = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -110,9 +136,13 @@ scf_status scf_bench_ceiling(int32_t kind, int32_t waves_per_simd, int32_t iters
         mfma_chains_kernel<1><<<nblk, 256>>>(out, iters, 0.999f, 1e-3f);
         flop_per_thread = 2.0 * 1024 * 32 * (double)iters / 64.0;
         break;
-      default:  // 32x32x2 = 2048 MACs
+      case 4:  // 32x32x2 = 2048 MACs
         mfma_chains_kernel<2><<<nblk, 256>>>(out, iters, 0.999f, 1e-3f);
         flop_per_thread = 2.0 * 2048 * 16 * (double)iters / 64.0;
+        break;
+      default:  // kinds 0 and 2 in one wave
+        mixed_chains_kernel<<<nblk, 256>>>(out, iters, 0.999f, 1e-3f);
+        flop_per_thread = 2.0 * 16 * 8 * (double)iters + 2.0 * 256 * 32 * (double)iters / 64.0;
         break;
     }
   };

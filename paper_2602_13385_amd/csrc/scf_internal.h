@@ -37,6 +37,8 @@ struct CoefArgs {
   const S* beta_rad;         // [(lmax+1)][(NMAXC+1)]  monic Gegenbauer recurrence
   const S* beta_ang;         // [(lmax+1)][(lmax+1)] monic Legendre recurrence [m][l], then 0..lmax
   acc_t<R>* partials;        // [nblocks][T]
+  int one_row;               // single-precision block kernel: every unit folds its
+                             // sums once, so it writes its hi row only (no lo row)
   int T, nmax;
   S binv, alpha, inv_alpha;
   int amode;
@@ -115,8 +117,11 @@ struct Engine {
   virtual int coef_variants() const = 0;
   // particles per wave-stage of variant v
   virtual int stage_particles(int v) const = 0;
-  // partial-sum rows written per wave-unit, and resident wave-units per CU
+  // partial-sum rows written per wave-unit (at most), and resident wave-units per CU
   virtual int rows_per_unit(int v) const = 0;
+  // stages a unit of variant v sums before it folds them into its rows; a
+  // unit of at most that many stages writes one row (0: rows_per_unit always)
+  virtual int fold_stages(int v) const = 0;
   virtual int max_resident_units(int v) const = 0;
   // launches variant v of the coefficient kernel over nunits wave-units
   virtual hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const = 0;
@@ -166,6 +171,12 @@ hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, i
                                    double* coef, void* W, int64_t W_stride,
                                    const double* centre_tab, int ncl, double* cur, int* step,
                                    hipStream_t s);
+// launch_reduce_batched + launch_finalize_batched in one pass, for few rows per cluster
+hipError_t launch_reduce_final_batched(int dtype, const void* partials, const int32_t* rows, int ncl,
+                                      int T, int nmax, int lmax, int nmaxc, const double* cs,
+                                      const double* fw, double* coef, void* W, int64_t W_stride,
+                                      const double* centre_tab, double* cur, int* step,
+                                      hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 // power per degree of ncl coefficient vectors (ncl x T in, ncl x (lmax+1) out)
 hipError_t launch_power(const double* coef, int nmax, int lmax, int ncl, double* El,

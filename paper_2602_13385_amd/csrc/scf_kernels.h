@@ -578,9 +578,11 @@ __device__ __forceinline__ void field_store(const ForceArgs<R>& a, const int64_t
     a.vx[i] = vx;
     a.vy[i] = vy;
     a.vz[i] = vz;
-    a.ax[i] = axv;
-    a.ay[i] = ayv;
-    a.az[i] = azv;
+    if (a.ax) {  // null on the steps whose accelerations no later step reads
+      a.ax[i] = axv;
+      a.ay[i] = ayv;
+      a.az[i] = azv;
+    }
     if (a.drift != R(0) || a.xo != a.x) {
       a.xo[i] = fma(a.drift, vx, x);
       a.yo[i] = fma(a.drift, vy, y);
@@ -1272,8 +1274,8 @@ coef_blk_kernel(CoefArgs<float> a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[n][j] = 0.f;
 
-  float* hi = a.partials + (int64_t)slot * 2 * a.T;
-  float* lo = hi + a.T;
+  float* hi = a.partials + (int64_t)slot * (a.one_row ? 1 : 2) * a.T;
+  float* lo = hi + a.T;  // (unused when one_row: the unit folds once)
   bool first_fold = true;
   int k = 0, since = 0;
   for (int64_t base = begin; base < end; base += P, ++k) {
@@ -1400,7 +1402,7 @@ coef_blk_kernel(CoefArgs<float> a) {
         const float v = rec[(tau_t * NR + n) * 4 + (c & 3)];
         if (first_fold) {
           hi[t] = v;
-          lo[t] = 0.f;
+          if (!a.one_row) lo[t] = 0.f;
         } else {
           const float h = hi[t];
           const float sum = h + v;
@@ -1456,6 +1458,10 @@ struct EngineImpl final : Engine {
   size_t real_size() const override { return sizeof(R); }
   int coef_variants() const override { return kBlk ? 1 : V::N; }
   int stage_particles(int v) const override { return kBlk ? BS::P : 64 / V::LPP[v]; }
+  int fold_stages(int v) const override {
+    (void)v;
+    return kBlk ? kCoefFold : 0;
+  }
   int rows_per_unit(int v) const override {
     if (kBlk) return 2;  // the (hi, lo) pair
     return v == 0 ? rows_t<V::LPP[0]>() : v == 1 ? rows_t<V::LPP[1]>() : rows_t<V::LPP[2]>();

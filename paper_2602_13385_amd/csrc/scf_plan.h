@@ -273,9 +273,11 @@ int coef_units(const scf_plan* p, int64_t n, int64_t* stages) {
   return coef_units_v(p, n, p->coef_variant, stages, p->coef_div);
 }
 
-// partial-sum rows of the current variant
-int coef_rows(const scf_plan* p, int units) {
-  return units * p->eng->rows_per_unit(p->coef_variant);
+// rows per unit of variant v when no unit sums more than max_stages stages:
+// one when each folds once (its compensation row would stay zero)
+int unit_rows(const scf_plan* p, int v, int64_t max_stages) {
+  const int f = p->eng->fold_stages(v);
+  return (f > 0 && max_stages <= f) ? 1 : p->eng->rows_per_unit(v);
 }
 
 // largest partial-row count over the coefficient variants (workspace sizing)
@@ -428,9 +430,10 @@ void fill_coef_common(CoefArgs<R>& ca, const scf_plan* p) {
 }
 
 // Sum of `rows` partial rows (FP32 or FP64) in double precision, then the
-// coefficients (coef, nullable) and force weights W.  Few rows: one pass;
+// coefficients (coef, nullable) and force weights W.  Up to kSmallRows rows:
+// one pass (16 coefficients per block of 1024 threads, 64 row groups);
 // otherwise chunk sums then their sum (two launches, fixed order either way).
-constexpr int kSmallRows = 512;
+constexpr int kSmallRows = 2048;
 
 scf_status reduce_and_finalize(scf_plan* p, const void* partials, int rows, double* coef, void* W,
                                char* ws, const WsLayout& L, hipStream_t s) {
@@ -460,7 +463,8 @@ scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
                       const void* m, double* coef, void* W, char* ws, const WsLayout& L, hipStream_t s) {
   int64_t stages;
   const int units = coef_units(p, n, &stages);
-  const int nb = coef_rows(p, units);
+  const int rpu = units > 0 ? unit_rows(p, p->coef_variant, (stages + units - 1) / units) : 1;
+  const int nb = units * rpu;
   if (n == 0) {
     // empty particle set: all coefficients vanish
     if (coef) {
@@ -483,6 +487,7 @@ scf_status run_coeffs(scf_plan* p, int64_t n, const void* x, const void* y, cons
   ca.n = n;
   ca.partials = (R*)(ws + L.partials);
   ca.nunits = units;
+  ca.one_row = rpu == 1;
   {
     Timed t(p, s, K_COEF);
     HIP_TRY(p->eng->launch_coef(&ca, units, p->coef_variant, s));

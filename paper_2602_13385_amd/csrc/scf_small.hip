@@ -66,38 +66,53 @@ __device__ __forceinline__ void finalize_block(const double* __restrict__ red1, 
   }
 }
 
-// Single-pass reduction for few partial rows: one block of 1024 threads per
-// 64 coefficients (16 row subsets, then their sum in a fixed order), then
-// the finalisation of those coefficients.
+// Single-pass reduction and finalisation of up to a few thousand partial
+// rows [r0, r1), for a block of 1024 threads and the 16 coefficients
+// t = 16 cb .. 16 cb + 15: thread (g, c) sums rows r0 + g, r0 + g + 64, ..
+// of coefficient 16 cb + c in double precision (each wave reads four 64-byte
+// row pieces per load), the 64 row-group sums of a coefficient are then added
+// pairwise in a fixed order, and a_t = cs_t * sum and W[(l,j)][n] = fw_t a_t
+// are written; rows n in (nmax, nmaxc] of W are zero.
 template <typename R>
-__global__ void __launch_bounds__(1024) reduce_final_small_kernel(
-    const R* __restrict__ partials, int nblocks, int T, int nmax, int lmax, int nmaxc,
-    const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W) {
-  __shared__ double sh[16][64];
-  const int ti = threadIdx.x & 63, kc = threadIdx.x >> 6;
-  const int t = blockIdx.x * 64 + ti;
+__device__ __forceinline__ void reduce_final_cols(const R* __restrict__ partials, int r0, int r1,
+                                                  int T, int nmax, int lmax, int nmaxc,
+                                                  const double* __restrict__ cs,
+                                                  const double* __restrict__ fw, double* coef,
+                                                  R* W, int cb, int ncb) {
+  __shared__ double sh[64][16];
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int t = cb * 16 + c;
   double s = 0.0;
   if (t < T) {
 #pragma unroll 8
-    for (int b = kc; b < nblocks; b += 16) s += double(partials[(int64_t)b * T + t]);
+    for (int b = r0 + g; b < r1; b += 64) s += double(partials[(int64_t)b * T + t]);
   }
-  sh[kc][ti] = s;
+  sh[g][c] = s;
   __syncthreads();
+  for (int h = 32; h >= 1; h >>= 1) {
+    if (g < h) sh[g][c] += sh[g + h][c];
+    __syncthreads();
+  }
   const int L2 = (lmax + 1) * (lmax + 1);
-  if (kc == 0 && t < T) {
-    double tot = 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) tot += sh[k][ti];
+  if (g == 0 && t < T) {
     const int n = t / L2, lj = t % L2;
-    const double cv = cs[t] * tot;
+    const double cv = cs[t] * sh[0][c];
     if (coef) coef[t] = cv;
     W[lj * (nmaxc + 1) + n] = R(fw[t] * cv);
   }
   const int npad = (nmaxc - nmax) * L2;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npad; q += gridDim.x * blockDim.x) {
+  for (int q = cb * blockDim.x + threadIdx.x; q < npad; q += ncb * blockDim.x) {
     const int n = nmax + 1 + q / L2, lj = q % L2;
     W[lj * (nmaxc + 1) + n] = R(0);
   }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(1024) reduce_final_small_kernel(
+    const R* __restrict__ partials, int nblocks, int T, int nmax, int lmax, int nmaxc,
+    const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W) {
+  reduce_final_cols<R>(partials, 0, nblocks, T, nmax, lmax, nmaxc, cs, fw, coef, W, blockIdx.x,
+                       gridDim.x);
 }
 
 template <typename R>
@@ -186,6 +201,28 @@ __global__ void __launch_bounds__(256) finalize_batched_kernel(
                     gridDim.x);
 }
 
+// Batched single-pass reduction and finalisation: block (cb, c) reduces
+// cluster c's rows [rows[c], rows[c+1]) for coefficients 16 cb .. 16 cb + 15
+// (as reduce_final_cols); block (0, 0) also copies row *step of the centre
+// table into cur and then advances *step (as finalize_batched_kernel).
+template <typename R>
+__global__ void __launch_bounds__(1024) reduce_final_batched_kernel(
+    const R* __restrict__ partials, const int32_t* __restrict__ rows, int T, int nmax, int lmax,
+    int nmaxc, const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W,
+    int64_t W_stride, const double* __restrict__ centre_tab, int ncl, double* cur, int* step) {
+  const int c = blockIdx.y;
+  if (blockIdx.x == 0 && c == 0 && step) {
+    const int k = *step;
+    for (int i = threadIdx.x; i < ncl * 9; i += blockDim.x)
+      cur[i] = centre_tab[(int64_t)k * ncl * 9 + i];
+    __syncthreads();
+    if (threadIdx.x == 0) *step = k + 1;
+  }
+  reduce_final_cols<R>(partials, rows[c], rows[c + 1], T, nmax, lmax, nmaxc, cs, fw,
+                       coef ? coef + (int64_t)c * T : nullptr, W + (int64_t)c * W_stride,
+                       blockIdx.x, gridDim.x);
+}
+
 __global__ void set_int_kernel(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
@@ -211,7 +248,7 @@ hipError_t launch_reduce_final_small(int dtype, const void* partials, int nblock
                                     int lmax, int nmaxc, const double* cs, const double* fw,
                                     double* coef, void* W, hipStream_t s) {
   if (T <= 0) return hipSuccess;
-  const int grid = (T + 63) / 64;
+  const int grid = (T + 15) / 16;
   if (dtype == 0)
     reduce_final_small_kernel<float><<<grid, 1024, 0, s>>>((const float*)partials, nblocks, T, nmax,
                                                            lmax, nmaxc, cs, fw, coef, (float*)W);
@@ -289,6 +326,24 @@ hipError_t launch_finalize_batched(int dtype, const double* red1, int nchunks, i
     finalize_batched_kernel<double><<<grid, 256, 0, s>>>(red1, nchunks, T, nmax, lmax, nmaxc, cs,
                                                          fw, coef, (double*)W, W_stride,
                                                          centre_tab, ncl, cur, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_final_batched(int dtype, const void* partials, const int32_t* rows, int ncl,
+                                      int T, int nmax, int lmax, int nmaxc, const double* cs,
+                                      const double* fw, double* coef, void* W, int64_t W_stride,
+                                      const double* centre_tab, double* cur, int* step,
+                                      hipStream_t s) {
+  if (ncl <= 0 || T <= 0) return hipSuccess;
+  dim3 grid((T + 15) / 16, ncl);
+  if (dtype == 0)
+    reduce_final_batched_kernel<float><<<grid, 1024, 0, s>>>(
+        (const float*)partials, rows, T, nmax, lmax, nmaxc, cs, fw, coef, (float*)W, W_stride,
+        centre_tab, ncl, cur, step);
+  else
+    reduce_final_batched_kernel<double><<<grid, 1024, 0, s>>>(
+        (const double*)partials, rows, T, nmax, lmax, nmaxc, cs, fw, coef, (double*)W, W_stride,
+        centre_tab, ncl, cur, step);
   return hipGetLastError();
 }
 

@@ -208,7 +208,8 @@ def _check(status):
 
 def bench_ceiling(kind, waves_per_simd, iters=20000):
     """scf_bench_ceiling: (TFLOP/s, ms) of a throughput microbenchmark
-    (kind 0/1: FP32 FMA chains, 2/3/4: FP32 MFMA 4x4x1 / 16x16x4 / 32x32x2)."""
+    (kind 0/1: FP32 FMA chains, 2/3/4: FP32 MFMA 4x4x1 / 16x16x4 / 32x32x2,
+    5: kinds 0 and 2 together in every wave)."""
     torch = _torch()
     scratch = torch.empty(8 * 4096, dtype=torch.float32, device="cuda")
     tf = C.c_double()

@@ -112,3 +112,14 @@ def test_cadence_density_frame_calls_reject_a_null_plan(S):
     assert L.scf_plan_get_basis(None, None) == 1
     for name in ("scf_select", "scf_evolve", "scf_tune_basis"):
         assert len(L.scf_last_error()) > 0, name
+
+
+def test_bench_ceiling_rejects_bad_arguments(S):
+    """The throughput microbenchmark checks kind (0..5), waves per SIMD (1..8)
+    and iters before any device call."""
+    L = S.lib()
+    tf, ms = C.c_double(), C.c_double()
+    dummy = C.c_void_p(256)  # never dereferenced: each call fails its argument check
+    for kind, wv, it in ((6, 4, 10), (-1, 4, 10), (0, 0, 10), (0, 9, 10), (5, 4, 0)):
+        assert L.scf_bench_ceiling(kind, wv, it, dummy, C.byref(tf), C.byref(ms)) == 1
+    assert L.scf_bench_ceiling(0, 4, 10, None, C.byref(tf), C.byref(ms)) == 1
