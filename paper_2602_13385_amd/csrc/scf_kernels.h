@@ -801,32 +801,60 @@ __device__ __forceinline__ void field_eval_mfma(const float x, const float y, co
     for (int n = 2; n <= NMAXC; ++n) p[n] = g.xi * p[n - 1] - tl[n] * p[n - 2];
     float psl = 0.f, rhl = 0.f, gxl = 0.f, gyl = 0.f, gzl = 0.f;
     float Qup = 0.f;
+    // (the first two degrees of an order, Qt_m^m = 1 and Qt_{m+1}^m = c, and
+    // dQt_m^m = 0, are written out: a product with a zero operand is not
+    // folded away under IEEE rules)
     auto legendre = [&](auto mc, float& Q, float& dQ) {
       constexpr int m = decltype(mc)::value;
-      Q = g.c * QR[m] - float(legendre_b(l, m)) * QW[m];
+      if constexpr (l == m)
+        Q = 1.f;
+      else if constexpr (l == m + 1)
+        Q = g.c;
+      else
+        Q = g.c * QR[m] - float(legendre_b(l, m)) * QW[m];
       QW[m] = Q;
-      dQ = float(l - m) * Qup;
+      if constexpr (l == m)
+        dQ = 0.f;
+      else
+        dQ = float(l - m) * Qup;
       Qup = Q;
     };
+    // The first order of a degree's sweep (m = l) starts its sums, and its dQ
+    // is zero; E_0 = 1 gives the order-1 gradient terms directly.  (Products
+    // with a zero or unit operand are not folded away under IEEE rules, so
+    // these cases are written out.)
     auto combine = [&](auto mc, const float Q, const float dQ, const mfma_f4 acc) {
       constexpr int m = decltype(mc)::value;
+      constexpr bool first = m == l;
+      auto add = [&](float& sum, const float u, const float v) {
+        if constexpr (first)
+          sum = u * v;
+        else
+          sum = fmaf(u, v, sum);
+      };
       const float sc = acc[0], dsc = acc[1];
       if constexpr (m == 0) {
-        psl = fmaf(Q, sc, psl);
-        rhl = fmaf(Q, dsc, rhl);
-        gzl = fmaf(dQ, sc, gzl);
+        add(psl, Q, sc);
+        add(rhl, Q, dsc);
+        if constexpr (!first) gzl = fmaf(dQ, sc, gzl);
       } else {
         const float ss = acc[2], dss = acc[3];
         const float v1 = sc * Er[m] + ss * Ei[m];
         const float v2 = dsc * Er[m] + dss * Ei[m];
-        const float v3 = sc * Er[m - 1] + ss * Ei[m - 1];
-        const float v4 = ss * Er[m - 1] - sc * Ei[m - 1];
+        float v3, v4;
+        if constexpr (m == 1) {
+          v3 = sc;
+          v4 = ss;
+        } else {
+          v3 = sc * Er[m - 1] + ss * Ei[m - 1];
+          v4 = ss * Er[m - 1] - sc * Ei[m - 1];
+        }
         const float mQ = float(m) * Q;
-        psl = fmaf(Q, v1, psl);
-        rhl = fmaf(Q, v2, rhl);
-        gzl = fmaf(dQ, v1, gzl);
-        gxl = fmaf(mQ, v3, gxl);
-        gyl = fmaf(mQ, v4, gyl);
+        add(psl, Q, v1);
+        add(rhl, Q, v2);
+        if constexpr (!first) gzl = fmaf(dQ, v1, gzl);
+        add(gxl, mQ, v3);
+        add(gyl, mQ, v4);
       }
     };
     // the sums are due at each call: this keeps the compiler from holding
@@ -865,11 +893,23 @@ __device__ __forceinline__ void field_eval_mfma(const float x, const float y, co
       });
       sums_due();
     });
-    psi = fmaf(Gl, psl, psi);
-    psir = fmaf(dGl, psl, fmaf(Gl * g.dxi, rhl, psir));
-    gx = fmaf(Gl, gxl, gx);
-    gy = fmaf(Gl, gyl, gy);
-    gz = fmaf(Gl, gzl, gz);
+    if constexpr (l == 0) {
+      // degree 0 starts the sums and has no angular gradient
+      psi = Gl * psl;
+      psir = fmaf(dGl, psl, (Gl * g.dxi) * rhl);
+    } else {
+      psi = fmaf(Gl, psl, psi);
+      psir = fmaf(dGl, psl, fmaf(Gl * g.dxi, rhl, psir));
+      if constexpr (l == 1) {
+        gx = Gl * gxl;
+        gy = Gl * gyl;
+        gz = Gl * gzl;
+      } else {
+        gx = fmaf(Gl, gxl, gx);
+        gy = fmaf(Gl, gyl, gy);
+        gz = fmaf(Gl, gzl, gz);
+      }
+    }
     // likewise the degree's contribution
     asm volatile("" : "+v"(psi), "+v"(psir), "+v"(gx), "+v"(gy), "+v"(gz));
   });
