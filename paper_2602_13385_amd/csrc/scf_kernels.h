@@ -1359,19 +1359,12 @@ coef_blk_kernel(CoefArgs<float> a) {
       float bl[NR];
 #pragma unroll
       for (int n = 2; n < NR; ++n) bl[n] = btab[tl * NR + n];
-      // operands of the next particle are loaded before this one's FMAs
       const float* rp = rec + grp * PS;
-      float4 av_n = *reinterpret_cast<const float4*>(rp + 4 * tau);
-      float xi_n = rp[XI];
 #pragma unroll 1
       for (int ii = 0; ii < PPG; ++ii) {
-        const float4 av = av_n;
-        const float xi = xi_n;
-        if (ii + 1 < PPG) {
-          rp += G * PS;
-          av_n = *reinterpret_cast<const float4*>(rp + 4 * tau);
-          xi_n = rp[XI];
-        }
+        const float4 av = *reinterpret_cast<const float4*>(rp + 4 * tau);
+        const float xi = rp[XI];
+        rp += G * PS;
         const float a4[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[0][j] += a4[j];
