@@ -18,7 +18,9 @@ Engine* find_engine_f64_generic(int nmax, int lmax) {
   SCF_ENGINE(20, 4)
   SCF_ENGINE(20, 5)
   SCF_ENGINE(20, 6)
+  SCF_ENGINE(20, 7)
   SCF_ENGINE(20, 8)
+  SCF_ENGINE(20, 9)
   SCF_ENGINE(20, 10)
   return nullptr;
 }
