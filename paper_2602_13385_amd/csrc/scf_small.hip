@@ -107,11 +107,21 @@ __device__ __forceinline__ void reduce_final_cols(const R* __restrict__ partials
   }
 }
 
+// Coefficient chunk of a block: blocks are dealt to the 8 XCDs in turn
+// (block b runs on XCD b mod 8), so chunk (b mod 8) per + b / 8 gives each
+// XCD a contiguous range of chunks, and the two 64-byte halves of a row's
+// 128-byte line are read through one L2 (the grid is a multiple of 8 blocks).
+__device__ __forceinline__ int xcd_chunk() {
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+constexpr int grid_chunks(int T) { return ((T + 15) / 16 + 7) / 8 * 8; }
+
 template <typename R>
 __global__ void __launch_bounds__(1024) reduce_final_small_kernel(
     const R* __restrict__ partials, int nblocks, int T, int nmax, int lmax, int nmaxc,
     const double* __restrict__ cs, const double* __restrict__ fw, double* coef, R* W) {
-  reduce_final_cols<R>(partials, 0, nblocks, T, nmax, lmax, nmaxc, cs, fw, coef, W, blockIdx.x,
+  reduce_final_cols<R>(partials, 0, nblocks, T, nmax, lmax, nmaxc, cs, fw, coef, W, xcd_chunk(),
                        gridDim.x);
 }
 
@@ -220,7 +230,7 @@ __global__ void __launch_bounds__(1024) reduce_final_batched_kernel(
   }
   reduce_final_cols<R>(partials, rows[c], rows[c + 1], T, nmax, lmax, nmaxc, cs, fw,
                        coef ? coef + (int64_t)c * T : nullptr, W + (int64_t)c * W_stride,
-                       blockIdx.x, gridDim.x);
+                       xcd_chunk(), gridDim.x);
 }
 
 __global__ void set_int_kernel(int* p, int v) {
@@ -248,7 +258,7 @@ hipError_t launch_reduce_final_small(int dtype, const void* partials, int nblock
                                     int lmax, int nmaxc, const double* cs, const double* fw,
                                     double* coef, void* W, hipStream_t s) {
   if (T <= 0) return hipSuccess;
-  const int grid = (T + 15) / 16;
+  const int grid = grid_chunks(T);
   if (dtype == 0)
     reduce_final_small_kernel<float><<<grid, 1024, 0, s>>>((const float*)partials, nblocks, T, nmax,
                                                            lmax, nmaxc, cs, fw, coef, (float*)W);
@@ -335,7 +345,7 @@ hipError_t launch_reduce_final_batched(int dtype, const void* partials, const in
                                       const double* centre_tab, double* cur, int* step,
                                       hipStream_t s) {
   if (ncl <= 0 || T <= 0) return hipSuccess;
-  dim3 grid((T + 15) / 16, ncl);
+  dim3 grid(grid_chunks(T), ncl);
   if (dtype == 0)
     reduce_final_batched_kernel<float><<<grid, 1024, 0, s>>>(
         (const float*)partials, rows, T, nmax, lmax, nmaxc, cs, fw, coef, (float*)W, W_stride,
