@@ -229,6 +229,13 @@ def run_batched(torch, scf, I, steps):
                 ms_graph = min(ms_graph, t)
             else:
                 ms = min(ms, t)
+    # per-kernel times of the direct launches (HIP events around each launch,
+    # in a separate run of the same length)
+    plan.profile(True)
+    plan.kernel_times()
+    cen, acc = plan.step_batched(off, st, m, w.dt, steps, host=host, centres=cen, acc=acc)
+    kt = {k: v[1] / steps for k, v in plan.kernel_times().items()}
+    plan.profile(False)
     # plain per-cluster steps on the same GPU, same particles
     parts = []
     for c in range(len(sizes)):
@@ -252,7 +259,8 @@ def run_batched(torch, scf, I, steps):
             "graph_ms_per_step": ms_graph / steps,
             "plain_per_cluster_value": N * T * steps / (ms_plain * 1e-3),
             "plain_per_cluster_ms_per_step": ms_plain / steps,
-            "speedup_vs_plain": ms_plain / ms, "graph_captures": plan.graph_captures}
+            "speedup_vs_plain": ms_plain / ms, "graph_captures": plan.graph_captures,
+            "kernels_ms_per_step": kt}
 
 
 def _energy(torch, plan, st, m):

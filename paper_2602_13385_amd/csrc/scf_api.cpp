@@ -700,24 +700,30 @@ scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offse
         Timed t(p, q, K_BATCH_COEF);
         HIP_TRY(p->eng->launch_coef(&ca, U, v, q));
       }
-      if (one_pass) {
-        HIP_TRY(launch_reduce_final_batched(p->dtype, ca.partials, (const int32_t*)(w + B.rows),
-                                            ncl, (int)p->T, p->nmax, p->lmax, p->nmaxc, p->d_cs,
-                                            p->d_fw, coef, Wb, W_stride, (const double*)(w + B.tab),
-                                            (double*)(w + B.cur), (int*)(w + B.ctr), q));
-      } else {
-        HIP_TRY(launch_reduce_batched(p->dtype, ca.partials, (const int32_t*)(w + B.rows), ncl,
-                                      (int)p->T, nch, (double*)(w + B.L.red1), q));
-        HIP_TRY(launch_finalize_batched(p->dtype, (const double*)(w + B.L.red1), nch, (int)p->T,
-                                        p->nmax, p->lmax, p->nmaxc, p->d_cs, p->d_fw, coef, Wb,
-                                        W_stride, (const double*)(w + B.tab), ncl,
-                                        (double*)(w + B.cur), (int*)(w + B.ctr), q));
+      {
+        Timed tr(p, q, K_REDUCE);
+        if (one_pass) {
+          HIP_TRY(launch_reduce_final_batched(
+              p->dtype, ca.partials, (const int32_t*)(w + B.rows), ncl, (int)p->T, p->nmax,
+              p->lmax, p->nmaxc, p->d_cs, p->d_fw, coef, Wb, W_stride,
+              (const double*)(w + B.tab), (double*)(w + B.cur), (int*)(w + B.ctr), q));
+        } else {
+          HIP_TRY(launch_reduce_batched(p->dtype, ca.partials, (const int32_t*)(w + B.rows), ncl,
+                                        (int)p->T, nch, (double*)(w + B.L.red1), q));
+          HIP_TRY(launch_finalize_batched(p->dtype, (const double*)(w + B.L.red1), nch, (int)p->T,
+                                          p->nmax, p->lmax, p->nmaxc, p->d_cs, p->d_fw, coef, Wb,
+                                          W_stride, (const double*)(w + B.tab), ncl,
+                                          (double*)(w + B.cur), (int*)(w + B.ctr), q));
+        }
       }
       ForceArgs<Rt> f2 = fa;
       f2.kick = Rt(kick);
       f2.drift = Rt(drift);
       if (!store_acc) f2.ax = f2.ay = f2.az = nullptr;
-      HIP_TRY(p->eng->launch_force(&f2, nblk, 1, p->field_variant, q));
+      {
+        Timed t(p, q, K_BATCH_FIELD);
+        HIP_TRY(p->eng->launch_force(&f2, nblk, 1, p->field_variant, q));
+      }
       return SCF_OK;
     };
     scf_status st = upload_rows(acc_valid ? 1 : 0);
