@@ -74,7 +74,7 @@ def roofline_entry(kernel, achieved, field_variant, traffic, flops, avg_ms):
     Packed FP32 is off in every HIP file here, so a vector-ALU kernel's own
     ceiling is the single-issue 78.6 TFLOP/s (`frac_single_issue_valu`, given
     for the vector-ALU kernels; measured FMA chains reach 75.6)."""
-    mfma = kernel == "field_step" and field_variant >= 2
+    mfma = kernel == "field_step" and field_variant in (2, 3)
     e = {"bound": "mfma" if mfma else "alu", "kernel": kernel, "achieved": achieved,
          "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
          "traffic": traffic, "flops_per_launch": flops, "avg_launch_ms": avg_ms}

@@ -426,7 +426,10 @@ scf_status scf_plan_get_basis(const scf_plan* plan, scf_basis* out);
  * partial rows when n is small).
  * scf_autotune times each (variant, divisor) on the given particles
  * (synchronising the stream) and keeps the fastest for the plan; best_ms
- * (nullable) receives its time.
+ * (nullable) receives its time per call in milliseconds.  Timing: one
+ * untimed call of each candidate, then three interleaved rounds of eight
+ * back-to-back calls per candidate; a candidate's time is its best round.
+ * scf_autotune_field times the field variants the same way.
  * Variants give results that agree to rounding (the particle sums are grouped
  * differently); a fixed variant is bitwise reproducible. */
 int32_t scf_plan_num_variants(const scf_plan* plan);
@@ -448,9 +451,14 @@ scf_status scf_autotune(scf_plan* plan, int64_t n, const void* x, const void* y,
  * persistent blocks, again under two register budgets (the compiler's own, or
  * 5 waves per SIMD); these two agree bitwise with each other and, since they
  * sum in another order, with variants 0 and 1 to the single-precision force
- * tolerance.  The batched step runs variant 1's kernel for variants 2 and 3
- * (its per-cluster blocks measured faster on the vector ALUs), and the
- * adjoint's accumulation pass always runs variant 0's.  scf_autotune_field
+ * tolerance.  The last two variants (4 and 5 in single, 2 and 3 in double
+ * precision) run the vector-ALU sums with each particle's degrees split over
+ * 2 or 4 waves of one block, which add their partial sums through LDS: more
+ * waves for few particles; they agree with variants 0 and 1 to the force
+ * tolerance of the plan's precision.  The batched step runs variant 1's
+ * kernel for every variant above 0 (its per-cluster blocks measured faster
+ * on the vector ALUs), and the adjoint's accumulation pass runs variant 0's
+ * for variants 0 to 3 and the split kernels for theirs.  scf_autotune_field
  * computes the coefficients of the given particles, times each variant on
  * the forces at those particles (written to ax, ay, az, device, caller-owned;
  * synchronising the stream) and keeps the fastest for the plan; best_ms

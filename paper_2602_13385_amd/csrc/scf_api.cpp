@@ -2,7 +2,52 @@
 // double-precision centre orbit (Sec. 2.1) and the launch sequences of the
 // hot path (coefficients, field, step, batched step, adjoint, diagnostics).
 // Declared in include/scf.h.
+#include <vector>
+
 #include "scf_plan.h"
+
+// Times ncand launch configurations (set(c) selects candidate c, launch()
+// runs it on stream s): one untimed launch of each first (code loading, clock
+// ramp), then three rounds over all candidates, each timing eight
+// back-to-back launches between a pair of events.  A candidate's time is its
+// best round; interleaving the rounds spreads clock drift over all
+// candidates alike.  best gets the fastest (the first of equals), best_ms its
+// time per launch.
+template <typename Set, typename Launch>
+static scf_status time_candidates(const int ncand, Set set, Launch launch, hipStream_t s,
+                                  int& best, float& best_ms) {
+  constexpr int kRounds = 3, kLaunches = 8;
+  std::vector<float> t(ncand, 1e30f);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  scf_status st = SCF_OK;
+  for (int c = 0; c < ncand && st == SCF_OK; ++c) {
+    set(c);
+    st = launch();
+  }
+  hipError_t he = hipSuccess;
+  for (int r = 0; r < kRounds && st == SCF_OK && he == hipSuccess; ++r)
+    for (int c = 0; c < ncand && st == SCF_OK && he == hipSuccess; ++c) {
+      set(c);
+      he = hipEventRecord(e0, s);
+      for (int k = 0; k < kLaunches && st == SCF_OK && he == hipSuccess; ++k) st = launch();
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (ms / kLaunches < t[c]) t[c] = ms / kLaunches;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SCF_OK) return st;
+  HIP_TRY(he);
+  best = 0;
+  for (int c = 1; c < ncand; ++c)
+    if (t[c] < t[best]) best = c;
+  best_ms = t[best];
+  return SCF_OK;
+}
 
 extern "C" {
 
@@ -63,49 +108,30 @@ scf_status scf_autotune(scf_plan* p, int64_t n, const void* x, const void* y, co
   if (!ws || ws_bytes < need)
     return fail(SCF_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
   if (!ws_aligned(ws)) return fail(SCF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-  hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
   double* coef = (double*)((char*)ws + ws_layout(p, n, 1, 0).coef);
-  const int saved = p->coef_variant;
+  const int saved = p->coef_variant, saved_div = p->coef_div;
   const bool prof = p->prof;
   p->prof = false;
-  const int saved_div = p->coef_div;
-  int best = saved, best_div = saved_div;
-  float bms = 1e30f;
-  for (int cand = 0; cand < 4 * p->eng->coef_variants(); ++cand) {
-    const int v = cand / 4, div = 1 << (cand % 4);
-    p->coef_variant = v;
-    p->coef_div = div;
-    float tot = 0.f;
-    for (int rep = 0; rep < 4; ++rep) {
-      HIP_TRY(hipEventRecord(e0, s));
-      scf_status st = scf_coeffs(p, n, x, y, z, m, coef, ws, ws_bytes, stream);
-      if (st != SCF_OK) {
-        p->coef_variant = saved;
-        p->coef_div = saved_div;
-        p->prof = prof;
-        return st;
-      }
-      HIP_TRY(hipEventRecord(e1, s));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (rep > 0) tot += ms;  // the first repetition warms up
-    }
-    if (tot < bms) {
-      bms = tot;
-      best = v;
-      best_div = div;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  p->coef_variant = best;
-  p->coef_div = best_div;
+  // candidates: every kernel variant at a block-count divisor of 1, 2, 4 or 8
+  int best = 0;
+  float bms = 0.f;
+  const scf_status st = time_candidates(
+      4 * p->eng->coef_variants(),
+      [&](int c) {
+        p->coef_variant = c / 4;
+        p->coef_div = 1 << (c % 4);
+      },
+      [&]() { return scf_coeffs(p, n, x, y, z, m, coef, ws, ws_bytes, stream); },
+      (hipStream_t)stream, best, bms);
   p->prof = prof;
-  if (best_ms) *best_ms = bms / 3.0;
+  if (st != SCF_OK) {
+    p->coef_variant = saved;
+    p->coef_div = saved_div;
+    return st;
+  }
+  p->coef_variant = best / 4;
+  p->coef_div = 1 << (best % 4);
+  if (best_ms) *best_ms = bms;
   return SCF_OK;
 }
 
@@ -145,48 +171,29 @@ scf_status scf_autotune_field(scf_plan* p, int64_t n, const void* x, const void*
     p->prof = prof;
     return st;
   }
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  int best = saved;
-  float bms = 1e30f;
-  for (int v = 0; v < p->eng->field_variants(); ++v) {
-    p->field_variant = v;
-    float tot = 0.f;
-    for (int rep = 0; rep < 4; ++rep) {
-      HIP_TRY(hipEventRecord(e0, s));
-      if (p->dtype == SCF_F32) {
-        HostParams<float> hp;
-        fill_host_params(hp, nullptr);
-        st = run_field<float>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, ax, ay,
-                              az, nullptr, w + L.W, hp, nullptr, 0, 0.0, 0.0, s);
-      } else {
-        HostParams<double> hp;
-        fill_host_params(hp, nullptr);
-        st = run_field<double>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, ax,
-                               ay, az, nullptr, w + L.W, hp, nullptr, 0, 0.0, 0.0, s);
-      }
-      if (st != SCF_OK) {
-        p->field_variant = saved;
-        p->prof = prof;
-        return st;
-      }
-      HIP_TRY(hipEventRecord(e1, s));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (rep > 0) tot += ms;
+  auto launch = [&]() -> scf_status {
+    if (p->dtype == SCF_F32) {
+      HostParams<float> hp;
+      fill_host_params(hp, nullptr);
+      return run_field<float>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, ax,
+                              ay, az, nullptr, w + L.W, hp, nullptr, 0, 0.0, 0.0, s);
     }
-    if (tot < bms) {
-      bms = tot;
-      best = v;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  p->field_variant = best;
+    HostParams<double> hp;
+    fill_host_params(hp, nullptr);
+    return run_field<double>(p, n, (void*)x, (void*)y, (void*)z, nullptr, nullptr, nullptr, ax,
+                             ay, az, nullptr, w + L.W, hp, nullptr, 0, 0.0, 0.0, s);
+  };
+  int best = 0;
+  float bms = 0.f;
+  st = time_candidates(
+      p->eng->field_variants(), [&](int c) { p->field_variant = c; }, launch, s, best, bms);
   p->prof = prof;
-  if (best_ms) *best_ms = bms / 3.0;
+  if (st != SCF_OK) {
+    p->field_variant = saved;
+    return st;
+  }
+  p->field_variant = best;
+  if (best_ms) *best_ms = bms;
   return SCF_OK;
 }
 

@@ -386,16 +386,17 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
 // R is float, double or Dual<T>; the tables (W, recurrence constants) are of
 // the scalar type.  The degree loop is a real (wave-uniform) loop so that only
 // one degree's radial vector is live.
-template <typename R, int NMAXC, int LMAX>
-__device__ __forceinline__ void field_eval(const R x, const R y, const R z,
-                                           const scalar_t<R>* __restrict__ W,
+// The sums of one point over the degrees [lo, hi] (RANGED) or all degrees:
+// psi, its radial derivative psir, and the angular gradient (gx, gy, gz) of
+// the form Gamma below.  The Legendre factors of degrees below lo are still
+// swept (their recurrence feeds the next degrees).
+template <typename R, int NMAXC, int LMAX, bool RANGED>
+__device__ __forceinline__ void field_sums(const Geom<R>& g, const scalar_t<R>* __restrict__ W,
                                            const scalar_t<R>* __restrict__ bR,
-                                           const scalar_t<R>* __restrict__ bA, scalar_t<R> binv,
-                                           scalar_t<R> alpha, scalar_t<R> inv_alpha, int amode,
-                                           R& psi, R& axv, R& ayv, R& azv) {
+                                           const scalar_t<R>* __restrict__ bA, const int lo,
+                                           const int hi, R& psi, R& psir, R& gx, R& gy, R& gz) {
   using Sc = scalar_t<R>;
   constexpr int L1 = LMAX + 1, NW = NMAXC + 1;
-  Geom<R> g = make_geom<R>(x, y, z, R(binv), R(alpha), R(inv_alpha), amode);
 
   R Er[L1], Ei[L1];
   Er[0] = R(1);
@@ -406,7 +407,10 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
     Ei[m] = Er[m - 1] * g.uy + Ei[m - 1] * g.ux;
   }
   psi = R(0);
-  R psir = R(0), gx = R(0), gy = R(0), gz = R(0);
+  psir = R(0);
+  gx = R(0);
+  gy = R(0);
+  gz = R(0);
   R Gprev = R(0), Gl = g.g0;
   // Degrees in pairs: the Legendre factors of degree l overwrite those of
   // degree l-2 (two arrays in ping-pong fashion), and the orders are a static
@@ -425,6 +429,14 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
     if (l > 0) {
       Gprev = Gl;
       Gl = Gl * g.w;
+    }
+    if (RANGED && (l < lo || l > hi)) {
+      // outside the range: only the Legendre factors advance
+      const Sc* __restrict__ bl = bA + l;
+#pragma unroll
+      for (int m = LMAX; m >= 0; --m)
+        if (m <= l) QW[m] = g.c * QR[m] - bl[m * L1] * QW[m];
+      return;
     }
     const Sc fl = Sc(l);
     const R dGl = fl * Gprev * g.om - (Sc(2) * fl + Sc(1)) * g.kap * Gl;
@@ -502,7 +514,13 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
     degree(l, QA, QB);
     if (l + 1 <= LMAX) degree(l + 1, QB, QA);
   }
-  // grad psi = psi_r rhat + (1/r) (Gamma - (rhat . Gamma) rhat)
+}
+
+// a = -grad psi from psir and Gamma: grad psi = psi_r rhat + (1/r) (Gamma -
+// (rhat . Gamma) rhat); zero at r = 0
+template <typename R>
+__device__ __forceinline__ void field_cartesian(const Geom<R>& g, const R psir, const R gx,
+                                                const R gy, const R gz, R& axv, R& ayv, R& azv) {
   const R rg = g.ux * gx + g.uy * gy + g.c * gz;
   axv = R(0);
   ayv = R(0);
@@ -512,6 +530,19 @@ __device__ __forceinline__ void field_eval(const R x, const R y, const R z,
     ayv = -(psir * g.uy + g.ir * (gy - rg * g.uy));
     azv = -(psir * g.c + g.ir * (gz - rg * g.c));
   }
+}
+
+template <typename R, int NMAXC, int LMAX>
+__device__ __forceinline__ void field_eval(const R x, const R y, const R z,
+                                           const scalar_t<R>* __restrict__ W,
+                                           const scalar_t<R>* __restrict__ bR,
+                                           const scalar_t<R>* __restrict__ bA, scalar_t<R> binv,
+                                           scalar_t<R> alpha, scalar_t<R> inv_alpha, int amode,
+                                           R& psi, R& axv, R& ayv, R& azv) {
+  const Geom<R> g = make_geom<R>(x, y, z, R(binv), R(alpha), R(inv_alpha), amode);
+  R psir, gx, gy, gz;
+  field_sums<R, NMAXC, LMAX, false>(g, W, bR, bA, 0, LMAX, psi, psir, gx, gy, gz);
+  field_cartesian<R>(g, psir, gx, gy, gz, axv, ayv, azv);
 }
 
 template <typename R, int MODE>
@@ -550,6 +581,88 @@ __device__ __forceinline__ void field_body(const ForceArgs<R>& a) {
   field_eval<R, NMAXC, LMAX>(x, y, z, W, a.beta_rad, a.beta_ang, a.binv, a.alpha, a.inv_alpha,
                              a.amode, psi, axv, ayv, azv);
   field_store<R, MODE>(a, i, x, y, z, psi, axv, ayv, azv, cx, cy, cz, gcx, gcy, gcz);
+}
+
+// Field kernel body with each point's degrees split over S parts (for few
+// particles: S times the waves, each with about 1/S of a point's work).  A
+// 256-thread block takes P = 256/S particles; thread j works on particle
+// j mod P and part j / P, which is uniform over a wave since P >= 64.  Part k
+// sums degrees DegreeSplit::begin[k] .. begin[k+1]-1, the parts above 0 hand
+// their partial sums to part 0 through LDS, and part 0 adds them and stores.
+//
+// The degree ranges minimise the largest part's cost, a degree costing
+// 2l + 3 units (its Gegenbauer sweep and the radial sums of its 2l + 1 order
+// columns, one unit being a sweep over n), with two more units charged to
+// part 0 for the additions, the Cartesian transform and the stores.
+template <int LMAX, int S>
+struct DegreeSplit {
+  int begin[S + 1] = {};
+  static constexpr int cost(int b, int e) { return e * (e + 2) - b * (b + 2); }
+  constexpr DegreeSplit() {
+    constexpr int L1 = LMAX + 1;
+    int best[S + 1][L1 + 1] = {};  // least largest cost of degrees [0, e) in k parts
+    int cut[S + 1][L1 + 1] = {};
+    for (int e = 0; e <= L1; ++e) best[1][e] = cost(0, e) + 2;
+    for (int k = 2; k <= S; ++k)
+      for (int e = 0; e <= L1; ++e) {
+        best[k][e] = 1 << 30;
+        for (int b = 0; b <= e; ++b) {
+          const int v = best[k - 1][b] > cost(b, e) ? best[k - 1][b] : cost(b, e);
+          if (v < best[k][e]) {
+            best[k][e] = v;
+            cut[k][e] = b;
+          }
+        }
+      }
+    begin[S] = L1;
+    for (int k = S; k >= 1; --k) begin[k - 1] = k == 1 ? 0 : cut[k][begin[k]];
+  }
+};
+template <typename R, int NMAXC, int LMAX, int MODE, int S>
+__device__ __forceinline__ void field_body_split(const ForceArgs<R>& a) {
+  static_assert(S >= 2 && 256 % S == 0 && 256 / S >= 64, "parts must be wave-uniform");
+  constexpr int P = 256 / S;
+  constexpr DegreeSplit<LMAX, S> sp{};
+  __shared__ R part[S - 1][5][P];
+  const int t = threadIdx.x % P;
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / P);
+  const int64_t i0 = (int64_t)blockIdx.x * P + t;
+  const bool live = i0 < a.n;
+  const int64_t i = live ? i0 : a.n - 1;  // every thread reaches the barrier
+  const R x = a.x[i], y = a.y[i], z = a.z[i];
+  const Geom<R> g = make_geom<R>(x, y, z, R(a.binv), R(a.alpha), R(a.inv_alpha), a.amode);
+  int lo = sp.begin[0], hi = sp.begin[1] - 1;
+#pragma unroll
+  for (int k = 1; k < S; ++k)
+    if (h == k) {
+      lo = sp.begin[k];
+      hi = sp.begin[k + 1] - 1;
+    }
+  R psi, psir, gx, gy, gz;
+  field_sums<R, NMAXC, LMAX, true>(g, a.W, a.beta_rad, a.beta_ang, lo, hi, psi, psir, gx, gy, gz);
+  if (h) {
+    part[h - 1][0][t] = psi;
+    part[h - 1][1][t] = psir;
+    part[h - 1][2][t] = gx;
+    part[h - 1][3][t] = gy;
+    part[h - 1][4][t] = gz;
+  }
+  __syncthreads();
+  if (!h) {
+#pragma unroll
+    for (int k = 0; k < S - 1; ++k) {
+      psi += part[k][0][t];
+      psir += part[k][1][t];
+      gx += part[k][2][t];
+      gy += part[k][3][t];
+      gz += part[k][4][t];
+    }
+    R axv, ayv, azv;
+    field_cartesian<R>(g, psir, gx, gy, gz, axv, ayv, azv);
+    if (live)
+      field_store<R, MODE>(a, i, x, y, z, psi, axv, ayv, azv, a.cx, a.cy, a.cz, a.gcx, a.gcy,
+                           a.gcz);
+  }
 }
 
 // Host tidal field and the stores of one particle: the forces (mode 0), the
@@ -616,6 +729,11 @@ template <typename R, int NMAXC, int LMAX, int MODE, bool BATCHED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
 field_kernel_o4(ForceArgs<R> a) {
   field_body<R, NMAXC, LMAX, MODE, BATCHED>(a);
+}
+template <typename R, int NMAXC, int LMAX, int MODE, int S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2)))
+field_kernel_split(ForceArgs<R> a) {
+  field_body_split<R, NMAXC, LMAX, MODE, S>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1546,10 +1664,14 @@ struct EngineImpl final : Engine {
     return hipGetLastError();
   }
   // field variants: 0 and 1 = VALU kernel under two register budgets; 2 and 3
-  // (single precision) = matrix-core kernel under two register budgets, for
-  // the plain force and step passes (the batched step runs variant 1's kernel
-  // for them, the adjoint's accumulation pass variant 0's)
-  int field_variants() const override { return sizeof(R) == 4 ? 4 : 2; }
+  // (single precision) = matrix-core kernel under two register budgets; the
+  // last two (4 and 5 in single, 2 and 3 in double precision) = VALU kernel
+  // with each point's degrees split over 2 or 4 waves.  The batched step runs
+  // variant 1's kernel for variants 1 to 3; the adjoint's accumulation pass
+  // runs variant 0's for variants 0 to 3 and the split kernels for theirs.
+  int field_variants() const override { return sizeof(R) == 4 ? 6 : 4; }
+  // the first split variant (two parts; the next one has four)
+  static constexpr int kSplitVariant = sizeof(R) == 4 ? 4 : 2;
   // resident blocks of a persistent kernel on the device
   template <typename K>
   static int64_t resident_blocks(K kernel) {
@@ -1568,7 +1690,7 @@ struct EngineImpl final : Engine {
     if (nblocks <= 0) return hipSuccess;
     const ForceArgs<R>& fa = *(const ForceArgs<R>*)args;
     if constexpr (sizeof(R) == 4) {
-      if (fv >= 2 && mode != 2 && !fa.blk_cluster) {
+      if ((fv == 2 || fv == 3) && mode != 2 && !fa.blk_cluster) {
         // nblocks tiles of 256 particles over at most one resident round of blocks
         static const int64_t cap[2] = {resident_blocks(field_mfma_kernel<NMAXC, LMAX, 1>),
                                        resident_blocks(field_mfma_kernel_o5<NMAXC, LMAX, 1>)};
@@ -1588,6 +1710,27 @@ struct EngineImpl final : Engine {
       }
     }
     const dim3 g((unsigned)nblocks);
+    if (fv >= kSplitVariant && !fa.blk_cluster) {
+      // 128 (two parts) or 64 (four parts) particles a block
+      const int64_t per = fv == kSplitVariant ? 128 : 64;
+      const dim3 gs((unsigned)((fa.n + per - 1) / per));
+      if (fv == kSplitVariant) {
+        if (mode == 0)
+          field_kernel_split<R, NMAXC, LMAX, 0, 2><<<gs, 256, 0, s>>>(fa);
+        else if (mode == 1)
+          field_kernel_split<R, NMAXC, LMAX, 1, 2><<<gs, 256, 0, s>>>(fa);
+        else
+          field_kernel_split<R, NMAXC, LMAX, 2, 2><<<gs, 256, 0, s>>>(fa);
+      } else {
+        if (mode == 0)
+          field_kernel_split<R, NMAXC, LMAX, 0, 4><<<gs, 256, 0, s>>>(fa);
+        else if (mode == 1)
+          field_kernel_split<R, NMAXC, LMAX, 1, 4><<<gs, 256, 0, s>>>(fa);
+        else
+          field_kernel_split<R, NMAXC, LMAX, 2, 4><<<gs, 256, 0, s>>>(fa);
+      }
+      return hipGetLastError();
+    }
     if (fv >= 1 && mode != 2) {
       if (fa.blk_cluster)
         field_kernel_o4<R, NMAXC, LMAX, 1, true><<<g, 256, 0, s>>>(fa);

@@ -48,9 +48,12 @@ def _rel(a, b):
 
 
 # fv: the plan's field variant (3 = the matrix-core field pass of FP32 plans,
-# which the segment's forward recompute uses)
+# which the segment's forward recompute uses; 5 in FP32 and 3 in FP64 = the
+# degrees of each particle split over 4 waves, in the forward recompute and
+# the accumulation pass)
 @pytest.mark.parametrize("dtype,host,fv", [("f64", True, 0), ("f32", True, 0), ("f64", False, 0),
-                                           ("f32", False, 0), ("f32", True, 3)])
+                                           ("f32", False, 0), ("f32", True, 3), ("f32", True, 5),
+                                           ("f64", True, 3)])
 def test_adjoint_matches_oracle(torch, S, O, dtype, host, fv):
     n, nmax, lmax, dt, nsteps = 3000, 10, 6, 0.005, 4
     print(f"[adjoint parity] {dtype} host={host} field variant {fv}", flush=True)

@@ -72,8 +72,10 @@ def _rel(a, ref):
     return np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)
 
 
-# field variants: 0 = vector-ALU field pass, 3 = matrix-core one (FP32 plans)
-@pytest.mark.parametrize("dtype,fv", [("f32", 0), ("f32", 3), ("f64", 0)])
+# field variants: 0 = vector-ALU field pass, 3 = matrix-core one (FP32 plans),
+# 4, 5 (FP32) and 2, 3 (FP64) = degrees split over 2 or 4 waves
+@pytest.mark.parametrize("dtype,fv", [("f32", 0), ("f32", 3), ("f32", 5), ("f64", 0),
+                                      ("f64", 2)])
 def test_step_frozen_matches_oracle(torch, S, O, dtype, fv):
     print(f"[cadence] step_frozen {dtype} field variant {fv}", flush=True)
     st0, m = _cluster(3000, 21, 1.0, dtype)

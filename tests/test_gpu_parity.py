@@ -283,11 +283,12 @@ def test_step_matches_oracle(torch, S, O, case, dtype):
     assert np.abs(out2 - out).max() <= split_tol * np.abs(out).max()
 
 
-@pytest.mark.parametrize("fv", [2, 3])
+@pytest.mark.parametrize("fv", [2, 3, 4, 5])
 @pytest.mark.parametrize("case", STEP_CASES, ids=lambda c: f"n{c[0]}l{c[1]}N{c[2]}")
-def test_step_with_matrix_core_field_matches_oracle(torch, S, O, case, fv):
+def test_step_with_other_field_variants_matches_oracle(torch, S, O, case, fv):
     """The fused kick-drift of the step (host field included) through the
-    matrix-core field variants, against the oracle's steps."""
+    matrix-core field variants (2, 3) and the split-degree ones (4, 5),
+    against the oracle's steps."""
     nmax, lmax, n, comps, centre, dt, nsteps = case
     print(f"[step parity, field variant {fv}] nmax={nmax} lmax={lmax} N={n}", flush=True)
     p = I.plummer(n, 900 + nsteps)
@@ -315,36 +316,38 @@ def test_step_with_matrix_core_field_matches_oracle(torch, S, O, case, fv):
 def test_field_variants_agree(torch, S, dtype):
     """Each pair of variants that runs one kernel under two register budgets
     (0 and 1 on the vector ALUs, 2 and 3 on the matrix cores in FP32) agrees
-    bitwise, and every variant is deterministic; the matrix-core pair sums in
-    another order and agrees with the vector pair to the force bar."""
+    bitwise, and every variant is deterministic; the matrix-core pair and the
+    last two variants (degrees split over 2 or 4 waves) sum in other orders
+    and agree with the vector pair to the force bar."""
     p = I.hernquist(20_000, 4242)
     plan = S.Plan(16, 10, dtype=dtype)
     x, y, z = (_dev(torch, p.pos[i], dtype) for i in range(3))
     m = _dev(torch, p.mass, dtype)
     c = plan.coeffs(x, y, z, m)
     nv = plan.num_field_variants
-    assert nv == (4 if dtype == "f32" else 2)
+    assert nv == (6 if dtype == "f32" else 4)
     outs = []
     for v in list(range(nv)) + [nv - 1]:
         plan.field_variant = v
         outs.append(plan.forces(x, y, z, c, host=([("nfw", (232.98, 20.0))], 1.0),
                                 centre=[20.0, 1.0, -2.0]))
     torch.cuda.synchronize()
-    for i, j in [(0, 1), (nv, nv - 1)] + ([(2, 3)] if nv > 2 else []):
+    for i, j in [(0, 1), (nv, nv - 1)] + ([(2, 3)] if nv > 4 else []):
         for a, b in zip(outs[i], outs[j]):
             assert torch.equal(a, b), (i, j)
-    if nv > 2:
-        g0 = np.stack([t.cpu().numpy() for t in outs[0]]).astype(np.float64)
-        g2 = np.stack([t.cpu().numpy() for t in outs[2]]).astype(np.float64)
-        assert force_err(g2, g0) <= TOL[dtype], force_err(g2, g0)
+    g0 = np.stack([t.cpu().numpy() for t in outs[0]]).astype(np.float64)
+    for k in ([2] if nv > 4 else []) + [nv - 2, nv - 1]:
+        gk = np.stack([t.cpu().numpy() for t in outs[k]]).astype(np.float64)
+        assert force_err(gk, g0) <= TOL[dtype], (k, force_err(gk, g0))
     plan.autotune(x, y, z, m)
     assert 0 <= plan.field_variant < nv
 
 
 @pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 255, 257, 1000])
 def test_matrix_core_field_small_and_ragged_counts(torch, S, O, n):
-    """Every lane of a wave joins the matrix-core chains; lanes past the end
-    evaluate the last particle and store nothing."""
+    """Every lane of a wave joins the matrix-core chains (and every thread of
+    split-degree variants reaches its barrier); lanes past the end evaluate
+    the last particle and store nothing."""
     p = I.plummer(max(n, 2), 900 + n)
     pos = _rounded(p.pos[:, :n], "f32")
     B = O.basis(10, 6)
@@ -352,7 +355,7 @@ def test_matrix_core_field_small_and_ragged_counts(torch, S, O, n):
     Pref, gref = O.field(B, ref, *pos)
     plan = S.Plan(10, 6, dtype="f32")
     x, y, z = (_dev(torch, pos[i], "f32") for i in range(3))
-    for fv in (2, 3):
+    for fv in (2, 3, 4, 5):
         plan.field_variant = fv
         guard = torch.full((n + 64,), 7.0, dtype=torch.float32, device="cuda")
         ax = guard[:n]
