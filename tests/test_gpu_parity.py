@@ -343,29 +343,34 @@ def test_field_variants_agree(torch, S, dtype):
     assert 0 <= plan.field_variant < nv
 
 
-@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 255, 257, 1000])
-def test_matrix_core_field_small_and_ragged_counts(torch, S, O, n):
-    """Every lane of a wave joins the matrix-core chains (and every thread of
-    split-degree variants reaches its barrier); lanes past the end evaluate
-    the last particle and store nothing."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 127, 129, 255, 257, 1000])
+def test_field_variants_small_and_ragged_counts(torch, S, O, n, dtype):
+    """Every lane of a wave joins the matrix-core chains (FP32 variants 2, 3)
+    and every thread of the split-degree variants (the last two) reaches its
+    barrier; lanes past the end evaluate the last particle and store
+    nothing."""
+    print(f"[ragged field] {dtype} n={n}", flush=True)
     p = I.plummer(max(n, 2), 900 + n)
-    pos = _rounded(p.pos[:, :n], "f32")
+    pos = _rounded(p.pos[:, :n], dtype)
     B = O.basis(10, 6)
-    ref = O.coeffs(B, *_rounded(p.pos, "f32"), _rounded(p.mass, "f32"))
+    ref = O.coeffs(B, *_rounded(p.pos, dtype), _rounded(p.mass, dtype))
     Pref, gref = O.field(B, ref, *pos)
-    plan = S.Plan(10, 6, dtype="f32")
-    x, y, z = (_dev(torch, pos[i], "f32") for i in range(3))
-    for fv in (2, 3, 4, 5):
+    plan = S.Plan(10, 6, dtype=dtype)
+    td = torch.float32 if dtype == "f32" else torch.float64
+    x, y, z = (_dev(torch, pos[i], dtype) for i in range(3))
+    nv = plan.num_field_variants
+    for fv in ((2, 3) if dtype == "f32" else ()) + (nv - 2, nv - 1):
         plan.field_variant = fv
-        guard = torch.full((n + 64,), 7.0, dtype=torch.float32, device="cuda")
+        guard = torch.full((n + 64,), 7.0, dtype=td, device="cuda")
         ax = guard[:n]
-        ay, az, pot = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
+        ay, az, pot = (torch.empty(n, dtype=td, device="cuda") for _ in range(3))
         plan.forces(x, y, z, torch.as_tensor(ref, device="cuda"), pot=True,
                     out=(ax, ay, az, pot))
         torch.cuda.synchronize()
         g = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()]).astype(np.float64)
-        assert force_err(g, gref) <= TOL["f32"], (fv, force_err(g, gref))
-        assert np.abs(pot.cpu().numpy() - Pref).max() / np.abs(Pref).max() <= TOL["f32"], fv
+        assert force_err(g, gref) <= TOL[dtype], (fv, force_err(g, gref))
+        assert np.abs(pot.cpu().numpy() - Pref).max() / np.abs(Pref).max() <= TOL[dtype], fv
         assert (guard[n:].cpu().numpy() == 7.0).all(), fv
 
 
