@@ -761,12 +761,25 @@ def main():
         if "f64" in legs:
             print("[bench] FP64", file=sys.stderr, flush=True)
             steps64 = max(1, args.steps // 4)
-            r64 = run_main("f64", steps64, max(1, args.warmup // 4), torch, scf, I, profile=False)
+            r64 = run_main("f64", steps64, max(1, args.warmup // 4), torch, scf, I, profile=True)
             tf64 = (fl["coef"] + fl["field_step"]) * n / (r64["ms"] / steps64 * 1e-3) / 1e12
+            k64 = {}
+            for k in ("coef", "field_step"):
+                if k in r64["kernels"]:
+                    cnt, tot = r64["kernels"][k]
+                    tfk = fl[k] * n / (tot / cnt * 1e-3) / 1e12
+                    k64[k] = {"avg_launch_ms": tot / cnt, "tflops": tfk,
+                              "frac_fp64_peak": tfk / PEAK_FP64_TFLOPS}
             out["f64"] = {"value": n * T * steps64 / (r64["ms"] * 1e-3),
                           "ms_per_step": r64["ms"] / steps64, "steps": steps64,
                           "step_tflops": tf64, "frac_fp64_peak": tf64 / PEAK_FP64_TFLOPS,
-                          "f32_over_f64_speed": (r64["ms"] / steps64) / ms_per_step}
+                          "f32_over_f64_speed": (r64["ms"] / steps64) / ms_per_step,
+                          "config": {"coef_variant": r64["variant"],
+                                     "field_variant": r64["field_variant"],
+                                     "coef_units_div": r64["coef_units_div"]},
+                          "kernels": k64,
+                          "kernels_ms_per_step": {k: v[1] / steps64
+                                                  for k, v in r64["kernels"].items()}}
             del r64["plan"]
         legs_fn = [("accuracy", "accuracy", lambda: accuracy_main(torch, scf, I)),
                    ("batched", "batched", lambda: run_batched(torch, scf, I, steps=1000)),
