@@ -1175,7 +1175,10 @@ __global__ void __launch_bounds__(256) hvp_kernel(HvpArgs<T> a) {
 //     tiles are summed pairwise through LDS and the result is added to the
 //     unit's (hi, lo) pair of partial rows with an error-free two-sum, so the
 //     single-precision sums run over at most FOLD * P / G particles whatever N
-//     is, and the rounding error of each fold is carried in lo.
+//     is, and the rounding error of each fold is carried in lo.  The same
+//     kernel in double precision (a variant of the double-precision plans)
+//     adds its folds into one partial row per unit, and its records take two
+//     128-bit loads per tile.
 // The l-block of a record holds [Re_0, 0, Re_1, Im_1, .., Re_l, Im_l] padded
 // with zeros to a multiple of 4 (so the sine-cosine pairs are 8-byte aligned
 // for 64-bit stores); the record stride PS is a multiple of 4 with PS/4 odd,
@@ -1223,32 +1226,32 @@ struct OrderUnits {
 };
 
 // u^M (complex) and w^M (real) by squaring, at compile time over M.
-template <int M>
-__device__ __forceinline__ void cpow_u(float ux, float uy, float& er, float& ei) {
+template <int M, typename R>
+__device__ __forceinline__ void cpow_u(R ux, R uy, R& er, R& ei) {
   if constexpr (M == 0) {
-    er = 1.f;
-    ei = 0.f;
+    er = R(1);
+    ei = R(0);
   } else if constexpr (M == 1) {
     er = ux;
     ei = uy;
   } else if constexpr (M % 2 == 0) {
-    float hr, hi;
+    R hr, hi;
     cpow_u<M / 2>(ux, uy, hr, hi);
     er = hr * hr - hi * hi;
-    ei = 2.f * hr * hi;
+    ei = R(2) * hr * hi;
   } else {
-    float hr, hi;
+    R hr, hi;
     cpow_u<M - 1>(ux, uy, hr, hi);
     er = hr * ux - hi * uy;
     ei = hr * uy + hi * ux;
   }
 }
-template <int M>
-__device__ __forceinline__ float rpow(float w) {
-  if constexpr (M == 0) return 1.f;
+template <int M, typename R>
+__device__ __forceinline__ R rpow(R w) {
+  if constexpr (M == 0) return R(1);
   else if constexpr (M == 1) return w;
   else if constexpr (M % 2 == 0) {
-    const float h = rpow<M / 2>(w);
+    const R h = rpow<M / 2>(w);
     return h * h;
   } else {
     return rpow<M - 1>(w) * w;
@@ -1256,72 +1259,88 @@ __device__ __forceinline__ float rpow(float w) {
 }
 
 // Monic Legendre factor Qt_l^m from the two previous degrees (Qt_m^m = 1,
-// Qt_{m+1}^m = c); order 0, whose even degrees carry a constant term, takes
-// its recurrence constants as float pairs (hi + lo) so that their rounding
-// leaves no bias in an isotropic average.
-template <int L, int M>
-__device__ __forceinline__ float legendre_next(float c, float Q1, float Q0) {
+// Qt_{m+1}^m = c); in single precision, order 0, whose even degrees carry a
+// constant term, takes its recurrence constants as float pairs (hi + lo) so
+// that their rounding leaves no bias in an isotropic average.
+template <int L, int M, typename R>
+__device__ __forceinline__ R legendre_next(R c, R Q1, R Q0) {
   if constexpr (L == M) {
-    return 1.f;
+    return R(1);
   } else if constexpr (L == M + 1) {
     return c;
-  } else if constexpr (M == 0) {
+  } else if constexpr (M == 0 && sizeof(R) == 4) {
     constexpr double gd = legendre_b(L, M);
     constexpr float ghi = float(gd);
     constexpr float glo = float(gd - double(ghi));
     return fmaf(-glo, Q0, c * Q1 - ghi * Q0);
   } else {
-    constexpr float gam = float(legendre_b(L, M));
+    constexpr R gam = R(legendre_b(L, M));
     return c * Q1 - gam * Q0;
   }
 }
 
+// record stores of 2 and 4 consecutive values (16- and 8-byte aligned slots
+// in single precision; two 16-byte stores for four doubles)
+__device__ __forceinline__ void store2(float* d, float a, float b) {
+  *reinterpret_cast<float2*>(d) = make_float2(a, b);
+}
+__device__ __forceinline__ void store4(float* d, float a, float b, float c, float e) {
+  *reinterpret_cast<float4*>(d) = make_float4(a, b, c, e);
+}
+__device__ __forceinline__ void store2(double* d, double a, double b) {
+  *reinterpret_cast<double2*>(d) = make_double2(a, b);
+}
+__device__ __forceinline__ void store4(double* d, double a, double b, double c, double e) {
+  *reinterpret_cast<double2*>(d) = make_double2(a, b);
+  *reinterpret_cast<double2*>(d + 2) = make_double2(c, e);
+}
+
 // The values of one order unit for one particle into its record r:
 // m G_l Qt_l^m {Re, Im}(u^m), with mg0 = m G_0 (zero for a padding particle).
-template <int LMAX, int U, typename AoffF>
-__device__ __forceinline__ void basis_unit(float* r, const Geom<float>& g, float mg0, AoffF aoff) {
+template <int LMAX, int U, typename R, typename AoffF>
+__device__ __forceinline__ void basis_unit(R* r, const Geom<R>& g, R mg0, AoffF aoff) {
   using OU = OrderUnits<LMAX>;
   constexpr int K = OU::kind(U), MA = OU::ma(U);
-  float era, eia, erb = 0.f, eib = 0.f;
+  R era, eia, erb = R(0), eib = R(0);
   cpow_u<MA>(g.ux, g.uy, era, eia);
   if constexpr (K == 2) {
     erb = era * g.ux - eia * g.uy;
     eib = era * g.uy + eia * g.ux;
   }
-  float G = mg0 * rpow<MA>(g.w);  // m G_l at l = MA
-  float Qa0 = 0.f, Qa1 = 0.f, Qb0 = 0.f, Qb1 = 0.f;
+  R G = mg0 * rpow<MA>(g.w);  // m G_l at l = MA
+  R Qa0 = R(0), Qa1 = R(0), Qb0 = R(0), Qb1 = R(0);
   static_for<MA, LMAX + 1>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
-    const float Qa = legendre_next<l, MA>(g.c, Qa1, Qa0);
+    const R Qa = legendre_next<l, MA>(g.c, Qa1, Qa0);
     Qa0 = Qa1;
     Qa1 = Qa;
-    const float va = Qa * G;
-    float* d = r + aoff(l);
+    const R va = Qa * G;
+    R* d = r + aoff(l);
     if constexpr (K == 0) {
       if constexpr (l == 0)
-        *reinterpret_cast<float4*>(d) = make_float4(va, 0.f, 0.f, 0.f);
+        store4(d, va, R(0), R(0), R(0));
       else
-        *reinterpret_cast<float2*>(d) = make_float2(va, 0.f);
+        store2(d, va, R(0));
     } else if constexpr (K == 1) {
-      *reinterpret_cast<float2*>(d + 2) = make_float2(va * era, va * eia);
+      store2(d + 2, va * era, va * eia);
     } else if constexpr (K == 2) {
-      float vb = 0.f;
+      R vb = R(0);
       if constexpr (l >= MA + 1) {
-        const float Qb = legendre_next<l, MA + 1>(g.c, Qb1, Qb0);
+        const R Qb = legendre_next<l, MA + 1>(g.c, Qb1, Qb0);
         Qb0 = Qb1;
         Qb1 = Qb;
         vb = Qb * G;
       }
-      *reinterpret_cast<float4*>(d + 2 * MA) = make_float4(va * era, va * eia, vb * erb, vb * eib);
+      store4(d + 2 * MA, va * era, va * eia, vb * erb, vb * eib);
     } else {
-      *reinterpret_cast<float4*>(d + 2 * MA) = make_float4(va * era, va * eia, 0.f, 0.f);
+      store4(d + 2 * MA, va * era, va * eia, R(0), R(0));
     }
     if constexpr (l < LMAX) G *= g.w;
   });
 }
 
-template <int LMAX, int WS, int W, typename AoffF>
-__device__ __forceinline__ void basis_wave(float* r, const Geom<float>& g, float mg0, AoffF aoff) {
+template <int LMAX, int WS, int W, typename R, typename AoffF>
+__device__ __forceinline__ void basis_wave(R* r, const Geom<R>& g, R mg0, AoffF aoff) {
   using OU = OrderUnits<LMAX>;
   static_for<0, OU::NU>([&](auto uc) {
     constexpr int u = decltype(uc)::value;
@@ -1329,7 +1348,7 @@ __device__ __forceinline__ void basis_wave(float* r, const Geom<float>& g, float
   });
 }
 
-template <int NMAXC, int LMAX>
+template <int NMAXC, int LMAX, typename R = float>
 struct BlkShape {
   static constexpr int JT = 4;
   static constexpr int NR = NMAXC + 1;
@@ -1339,34 +1358,60 @@ struct BlkShape {
   static constexpr int XI = AL;       // slot of xi
   static constexpr int PS = ((AL / 4 + 1) % 2 == 1) ? (AL / 4 + 1) * 4 : (AL / 4 + 2) * 4;
   // a stage holds SLABS slabs of up to 64 particles (one particle per lane in
-  // the basis phase): the most (1, 2 or 4) whose records fit 39 KB, so that
-  // four blocks share a compute unit's LDS
-  static constexpr int LDS_REC = 39 * 1024 - 4 * (LMAX + 1) * NR;
-  static constexpr int SLABS = (4 * 64 * PS * 4 <= LDS_REC) ? 4 : ((2 * 64 * PS * 4 <= LDS_REC) ? 2 : 1);
+  // the basis phase): the most (1, 2 or 4) whose records fit 39 KB (single
+  // precision: four blocks share a compute unit's LDS) or 78 KB (double: two)
+  static constexpr int RB = (int)sizeof(R);
+  static constexpr int LDS_REC = (RB == 4 ? 39 : 78) * 1024 - RB * (LMAX + 1) * NR;
+  static constexpr int SLABS =
+      (4 * 64 * PS * RB <= LDS_REC) ? 4 : ((2 * 64 * PS * RB <= LDS_REC) ? 2 : 1);
   static constexpr int WS = 4 / SLABS;  // waves sharing a slab (they split its order units)
   static constexpr int G = (THREADS / NT) > 64 ? 64 : (THREADS / NT);
   static constexpr int PPG = (64 * SLABS) / G;  // particles per group and stage
   static constexpr int P = G * PPG;             // particles per stage
-  static constexpr int SLOT = NT * NR * JT;   // floats of one group's tiles
+  static constexpr int SLOT = NT * NR * JT;   // values of one group's tiles
   static constexpr int NSLOT = (P * PS) / SLOT;  // group tiles the stage buffer holds
   static constexpr int aoff(int l) { return JT * ntiles_c(l - 1, JT); }
   static_assert(G >= 1 && NT * G <= THREADS, "tiles must fit the block");
   static_assert(NSLOT >= 1, "the stage buffer must hold one group's tiles");
 };
 
-// waves per SIMD the block kernel is compiled for: 4 (at most 128 registers)
-// when its tiles have at most 17 rows, else 3
-template <int NMAXC>
-constexpr int blk_waves() { return NMAXC <= 16 ? 4 : 3; }
+// waves per SIMD the block kernel is compiled for: single precision 4 (at
+// most 128 registers) when its tiles have at most 17 rows, else 3; double
+// precision 2
+template <int NMAXC, typename R>
+constexpr int blk_waves() { return sizeof(R) == 8 ? 2 : (NMAXC <= 16 ? 4 : 3); }
 
-template <int NMAXC, int LMAX, int FOLD>
+// four consecutive record values (one 16-byte load in single precision, two
+// in double)
+__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+__device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
+  const double2 q0 = *reinterpret_cast<const double2*>(p);
+  const double2 q1 = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = q0.x;
+  v[1] = q0.y;
+  v[2] = q1.x;
+  v[3] = q1.y;
+}
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return fma(a, b, c); }
+
+// Block coefficient kernel.  R = float is the single-precision pass with
+// compensated folds into (hi, lo) rows; R = double (a variant of the
+// double-precision plans) adds its folds into one double row per unit.
+template <int NMAXC, int LMAX, int FOLD, typename R = float>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(blk_waves<NMAXC>(), blk_waves<NMAXC>())))
-coef_blk_kernel(CoefArgs<float> a) {
-  using S = BlkShape<NMAXC, LMAX>;
+__attribute__((amdgpu_waves_per_eu(blk_waves<NMAXC, R>(), blk_waves<NMAXC, R>())))
+coef_blk_kernel(CoefArgs<R> a) {
+  using S = BlkShape<NMAXC, LMAX, R>;
   constexpr int NR = S::NR, NT = S::NT, G = S::G, P = S::P, PS = S::PS, XI = S::XI;
   constexpr int PPG = S::PPG, SLOT = S::SLOT, NSLOT = S::NSLOT, L2 = (LMAX + 1) * (LMAX + 1);
-  __shared__ __align__(16) float rec[P * PS];
+  __shared__ __align__(16) R rec[P * PS];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int grp = tid / NT, tau = tid % NT;
@@ -1387,7 +1432,7 @@ coef_blk_kernel(CoefArgs<float> a) {
   }
   // radial recurrence constants of every degree, read per stage from LDS so
   // that they are not live through the basis phase
-  __shared__ __align__(16) float btab[(LMAX + 1) * NR];
+  __shared__ __align__(16) R btab[(LMAX + 1) * NR];
   for (int i = tid; i < (LMAX + 1) * NR; i += 256) btab[i] = a.beta_rad[i];
 
   // particle range and partial-row pair of this unit
@@ -1413,7 +1458,7 @@ coef_blk_kernel(CoefArgs<float> a) {
   // past the range.
   constexpr int WS = S::WS;
   const int sub = wave % WS, q = (wave / WS) * 64 + lane;
-  float px, py, pz, pm, pw;
+  R px, py, pz, pm, pw;
   {
     const int64_t gi0 = begin + q;
     const bool ok = q < P && gi0 < end;
@@ -1422,28 +1467,28 @@ coef_blk_kernel(CoefArgs<float> a) {
     py = a.y[gi];
     pz = a.z[gi];
     pm = a.m[gi];
-    pw = ok ? 1.f : 0.f;
+    pw = ok ? R(1) : R(0);
   }
   __syncthreads();
 
-  float acc[NR][4];
+  R acc[NR][4];
 #pragma unroll
   for (int n = 0; n < NR; ++n)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[n][j] = 0.f;
+    for (int j = 0; j < 4; ++j) acc[n][j] = R(0);
 
-  float* hi = a.partials + (int64_t)slot * (a.one_row ? 1 : 2) * a.T;
-  float* lo = hi + a.T;  // (unused when one_row: the unit folds once)
+  R* hi = a.partials + (int64_t)slot * (a.one_row ? 1 : 2) * a.T;
+  [[maybe_unused]] R* lo = hi + a.T;  // (single precision; unused when one_row)
   bool first_fold = true;
   int k = 0, since = 0;
   for (int64_t base = begin; base < end; base += P, ++k) {
     // ---- basis phase: every wave evaluates the geometry of the stage's
     // particles and the values of its own order units ------------------------
     if (q < P) {
-      float* r = rec + q * PS;
-      const Geom<float> g = make_geom<float>(px, py, pz, a.binv, a.alpha, a.inv_alpha, a.amode);
+      R* r = rec + q * PS;
+      const Geom<R> g = make_geom<R>(px, py, pz, a.binv, a.alpha, a.inv_alpha, a.amode);
       if (sub == 0) r[XI] = g.xi;
-      const float mg0 = (pm * pw) * g.g0;
+      const R mg0 = (pm * pw) * g.g0;
       auto aoff = [](int l) { return S::aoff(l); };
       if constexpr (WS == 1) {
         basis_wave<LMAX, 1, 0>(r, g, mg0, aoff);
@@ -1469,32 +1514,32 @@ coef_blk_kernel(CoefArgs<float> a) {
       py = a.y[gi];
       pz = a.z[gi];
       pm = a.m[gi];
-      pw = ok ? 1.f : 0.f;
+      pw = ok ? R(1) : R(0);
     }
     __syncthreads();
     // ---- accumulation phase -----------------------------------------------
     if (tv) {
-      float bl[NR];
+      R bl[NR];
 #pragma unroll
       for (int n = 2; n < NR; ++n) bl[n] = btab[tl * NR + n];
-      const float* rp = rec + grp * PS;
+      const R* rp = rec + grp * PS;
 #pragma unroll 1
       for (int ii = 0; ii < PPG; ++ii) {
-        const float4 av = *reinterpret_cast<const float4*>(rp + 4 * tau);
-        const float xi = rp[XI];
+        R a4[4];
+        load4(rp + 4 * tau, a4);
+        const R xi = rp[XI];
         rp += G * PS;
-        const float a4[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[0][j] += a4[j];
         if constexpr (NR > 1) {
-          float p0 = 1.f, p1 = xi;
+          R p0 = R(1), p1 = xi;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[1][j] = fmaf(p1, a4[j], acc[1][j]);
+          for (int j = 0; j < 4; ++j) acc[1][j] = fma_r(p1, a4[j], acc[1][j]);
 #pragma unroll
           for (int n = 2; n < NR; ++n) {
-            const float p2 = n == 2 ? fmaf(xi, p1, -bl[2]) : fmaf(xi, p1, -bl[n] * p0);
+            const R p2 = n == 2 ? fma_r(xi, p1, -bl[2]) : fma_r(xi, p1, -bl[n] * p0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[n][j] = fmaf(p2, a4[j], acc[n][j]);
+            for (int j = 0; j < 4; ++j) acc[n][j] = fma_r(p2, a4[j], acc[n][j]);
             p0 = p1;
             p1 = p2;
           }
@@ -1511,22 +1556,21 @@ coef_blk_kernel(CoefArgs<float> a) {
         for (int c0 = 0; c0 < movers; c0 += NSLOT) {
           const int c1 = movers < c0 + NSLOT ? movers : c0 + NSLOT;
           if (tv && grp >= half + c0 && grp < half + c1) {
-            float* d = rec + (grp - half - c0) * SLOT + tau * NR * 4;
+            R* d = rec + (grp - half - c0) * SLOT + tau * NR * 4;
 #pragma unroll
-            for (int n = 0; n < NR; ++n)
-              *reinterpret_cast<float4*>(d + 4 * n) =
-                  make_float4(acc[n][0], acc[n][1], acc[n][2], acc[n][3]);
+            for (int n = 0; n < NR; ++n) store4(d + 4 * n, acc[n][0], acc[n][1], acc[n][2], acc[n][3]);
           }
           __syncthreads();
           if (tv && grp >= c0 && grp < c1) {
-            const float* s = rec + (grp - c0) * SLOT + tau * NR * 4;
+            const R* s = rec + (grp - c0) * SLOT + tau * NR * 4;
 #pragma unroll
             for (int n = 0; n < NR; ++n) {
-              const float4 v = *reinterpret_cast<const float4*>(s + 4 * n);
-              acc[n][0] += v.x;
-              acc[n][1] += v.y;
-              acc[n][2] += v.z;
-              acc[n][3] += v.w;
+              R v[4];
+              load4(s + 4 * n, v);
+              acc[n][0] += v[0];
+              acc[n][1] += v[1];
+              acc[n][2] += v[2];
+              acc[n][3] += v[3];
             }
           }
           __syncthreads();
@@ -1537,11 +1581,9 @@ coef_blk_kernel(CoefArgs<float> a) {
       // group 0 leaves its tiles in the stage buffer; every thread then folds
       // coefficients t = tid, tid + 256, .. (coalesced rows)
       if (tv && grp == 0) {
-        float* d = rec + tau * NR * 4;
+        R* d = rec + tau * NR * 4;
 #pragma unroll
-        for (int n = 0; n < NR; ++n)
-          *reinterpret_cast<float4*>(d + 4 * n) =
-              make_float4(acc[n][0], acc[n][1], acc[n][2], acc[n][3]);
+        for (int n = 0; n < NR; ++n) store4(d + 4 * n, acc[n][0], acc[n][1], acc[n][2], acc[n][3]);
       }
       __syncthreads();
       for (int t = tid; t < a.T; t += 256) {
@@ -1550,23 +1592,26 @@ coef_blk_kernel(CoefArgs<float> a) {
         // column of j in the l-block, and the tile holding it
         const int c = j == 0 ? 0 : j + 1;
         const int tau_t = (l == 0 ? 0 : l + (l - 1) * (l - 1) / 4) + (c >> 2);
-        const float v = rec[(tau_t * NR + n) * 4 + (c & 3)];
+        const R v = rec[(tau_t * NR + n) * 4 + (c & 3)];
         if (first_fold) {
           hi[t] = v;
-          if (!a.one_row) lo[t] = 0.f;
-        } else {
+          if constexpr (sizeof(R) == 4)
+            if (!a.one_row) lo[t] = 0.f;
+        } else if constexpr (sizeof(R) == 4) {
           const float h = hi[t];
           const float sum = h + v;
           const float bp = sum - h;
           const float err = (h - (sum - bp)) + (v - bp);
           hi[t] = sum;
           lo[t] = lo[t] + err;
+        } else {
+          hi[t] = hi[t] + v;  // double precision: one row, plain sums
         }
       }
 #pragma unroll
       for (int n = 0; n < NR; ++n)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[n][j] = 0.f;
+        for (int j = 0; j < 4; ++j) acc[n][j] = R(0);
       first_fold = false;
       since = 0;
 
@@ -1600,21 +1645,24 @@ template <typename R, int NMAXC, int LMAX>
 struct EngineImpl final : Engine {
   using V = CoefVariants<R>;
   // Single-precision plans have one coefficient kernel, the block kernel with
-  // compensated folds; double-precision plans have the V::N wave-unit variants.
+  // compensated folds; double-precision plans have the V::N wave-unit variants
+  // and the block kernel as variant V::N.
   static constexpr bool kBlk = sizeof(R) == 4;
-  using BS = BlkShape<NMAXC, LMAX>;
+  using BS = BlkShape<NMAXC, LMAX, R>;
+  static bool is_blk(int v) { return kBlk || v == V::N; }
   int nmaxc() const override { return NMAXC; }
   int lmax() const override { return LMAX; }
   int dtype() const override { return sizeof(R) == 4 ? 0 : 1; }
   size_t real_size() const override { return sizeof(R); }
-  int coef_variants() const override { return kBlk ? 1 : V::N; }
-  int stage_particles(int v) const override { return kBlk ? BS::P : 64 / V::LPP[v]; }
+  int coef_variants() const override { return kBlk ? 1 : V::N + 1; }
+  int stage_particles(int v) const override { return is_blk(v) ? BS::P : 64 / V::LPP[v]; }
   int fold_stages(int v) const override {
     (void)v;
-    return kBlk ? kCoefFold : 0;
+    return is_blk(v) ? kCoefFold : 0;
   }
   int rows_per_unit(int v) const override {
-    if (kBlk) return 2;  // the (hi, lo) pair
+    if (kBlk) return 2;     // the (hi, lo) pair
+    if (v == V::N) return 1;  // double block kernel: one row
     return v == 0 ? rows_t<V::LPP[0]>() : v == 1 ? rows_t<V::LPP[1]>() : rows_t<V::LPP[2]>();
   }
   template <int LPP>
@@ -1625,13 +1673,12 @@ struct EngineImpl final : Engine {
   int max_resident_units(int v) const override {
     int per_cu = 0;
     hipError_t e;
-    if constexpr (kBlk) {
-      (void)v;
+    if (is_blk(v)) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, coef_blk_kernel<NMAXC, LMAX, kCoefFold>, 256, 0);
+          &per_cu, coef_blk_kernel<NMAXC, LMAX, kCoefFold, R>, 256, 0);
       if (e != hipSuccess || per_cu <= 0) per_cu = 1;
       return per_cu;  // a unit is a block of four waves
-    } else {
+    } else if constexpr (!kBlk) {
       if (v == 0)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu, coef_kernel<R, NMAXC, LMAX, V::LPP[0], V::WPB[0]>, 64 * V::WPB[0], 0);
@@ -1644,14 +1691,14 @@ struct EngineImpl final : Engine {
       if (e != hipSuccess || per_cu <= 0) per_cu = 1;
       return per_cu * V::WPB[v];
     }
+    return 1;
   }
   hipError_t launch_coef(const void* args, int nunits, int v, hipStream_t s) const override {
     if (nunits <= 0) return hipSuccess;
     const CoefArgs<R>& ca = *(const CoefArgs<R>*)args;
-    if constexpr (kBlk) {
-      (void)v;
-      coef_blk_kernel<NMAXC, LMAX, kCoefFold><<<nunits, 256, 0, s>>>(ca);
-    } else {
+    if (is_blk(v)) {
+      coef_blk_kernel<NMAXC, LMAX, kCoefFold, R><<<nunits, 256, 0, s>>>(ca);
+    } else if constexpr (!kBlk) {
       const int wpb = V::WPB[v];
       const int nblocks = (nunits + wpb - 1) / wpb;
       if (v == 0)
@@ -1786,8 +1833,10 @@ struct EngineImpl final : Engine {
       using S0 = CoefShape<R, NMAXC, LMAX, V::LPP[0]>;
       using S2 = CoefShape<R, NMAXC, LMAX, V::LPP[2]>;
       snprintf(buf, sizeof(buf),
-               "f64 nmax<=%d lmax=%d coef tiles %dx%d (groups %d|%d, tiles/lane %d|%d)", NMAXC,
-               LMAX, S0::NR, S0::JT, S0::G, S2::G, S0::KT, S2::KT);
+               "f64 nmax<=%d lmax=%d coef tiles %dx%d (groups %d|%d, tiles/lane %d|%d); block "
+               "variant %d x %d tiles, %d groups, %d particles per stage",
+               NMAXC, LMAX, S0::NR, S0::JT, S0::G, S2::G, S0::KT, S2::KT, BS::NR, BS::JT, BS::G,
+               BS::P);
     }
     return buf;
   }
