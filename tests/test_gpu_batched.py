@@ -81,11 +81,14 @@ def _run(torch, S, plan, off, st0, m, cens, dtype, dt, nsteps, graph=False, coef
 
 
 # fv: the plan's field variant (the batched step runs variant 1's kernel for the
-# matrix-core variants 2 and 3 of FP32 plans)
-@pytest.mark.parametrize("dtype,fv", [("f32", 0), ("f32", 2), ("f32", 3), ("f64", 0)])
-def test_batched_matches_oracle(torch, S, O, dtype, fv):
+# matrix-core variants 2 and 3 of FP32 plans); cv: the coefficient variant (3 =
+# the block kernel of FP64 plans)
+@pytest.mark.parametrize("dtype,fv,cv", [("f32", 0, 0), ("f32", 2, 0), ("f32", 3, 0),
+                                         ("f64", 0, 0), ("f64", 0, 3)])
+def test_batched_matches_oracle(torch, S, O, dtype, fv, cv):
     sizes = [3000, 0, 11000, 6173, 1]
-    print(f"[batched parity] sizes={sizes} {dtype} field variant {fv}", flush=True)
+    print(f"[batched parity] sizes={sizes} {dtype} field variant {fv} coefficient variant {cv}",
+          flush=True)
     off, st0, m, cens = _clusters(sizes, 4401)
     st0, m = _rounded(st0, dtype), _rounded(m, dtype)
     dt, nsteps = 0.005, 4
@@ -93,6 +96,7 @@ def test_batched_matches_oracle(torch, S, O, dtype, fv):
     st_ref, cen_ref, coef_ref = O.step_batched(B, _ohost(O), off, st0, m, cens, dt, nsteps)
     plan = S.Plan(10, 6, dtype=dtype)
     plan.field_variant = fv
+    plan.variant = cv
     coef = torch.empty(len(sizes) * plan.T, dtype=torch.float64, device="cuda")
     out, cen, _ = _run(torch, S, plan, off, st0, m, cens, dtype, dt, nsteps, coef=coef)
     assert np.abs(cen - cen_ref).max() <= 1e-12
