@@ -150,6 +150,24 @@ scf_status scf_step(scf_plan* plan, int64_t n, void* x, void* y, void* z, void* 
                     const scf_host* host, double* centre, double dt, int32_t nsteps,
                     double* coef_last, void* ws, size_t ws_bytes, void* stream);
 
+/* Elements of one force-weight row of the plan, (nmax bound + 1)(lmax + 1)^2:
+ * the coefficients of Eq. (total_potential) times their normalisations, in
+ * the plan's real type, as the field kernels read them. */
+int64_t scf_plan_weights_size(const scf_plan* plan);
+
+/* scf_step that also keeps the force weights of every kick: row k of w_hist
+ * (device, (nsteps + 1) * scf_plan_weights_size(plan) elements of the plan's
+ * real type, caller-owned) receives the weights from the coefficients at x_k,
+ * k = 1..nsteps, and row 0 those at the starting positions when the call
+ * evaluates a(x0) (without SCF_STEP_ACC_VALID; otherwise row 0 is left as it
+ * is).  The rows let scf_step_adjoint replay the segment without its
+ * coefficient passes.  Everything else is as for scf_step. */
+scf_status scf_step_keep_weights(scf_plan* plan, int64_t n, void* x, void* y, void* z, void* vx,
+                                 void* vy, void* vz, const void* m, void* ax, void* ay, void* az,
+                                 uint32_t step_flags, const scf_host* host, double* centre,
+                                 double dt, int32_t nsteps, double* coef_last, void* w_hist,
+                                 void* ws, size_t ws_bytes, void* stream);
+
 /* scf_step for nclusters independent clusters concatenated in the particle
  * arrays: cluster c owns particles [offsets[c], offsets[c+1]) (host array of
  * nclusters+1 entries, offsets[0] = 0, non-decreasing; n = offsets[nclusters]).
@@ -183,12 +201,17 @@ scf_status scf_step_batched(scf_plan* plan, int32_t nclusters, const int64_t* of
  * arrays (x, y, z, vx, vy, vz components) holding dL/d(final state) on entry
  * and dL/d(initial state) on return; lam_centre[6] (host, in/out) likewise
  * for the centre R, V; grad_host (host, host->ncomp*3 doubles) accumulates
- * dL/d(host parameters p[]).  Blocks until the results are on the host. */
+ * dL/d(host parameters p[]).  w_hist (device, nullable) holds the force
+ * weights of the segment's kicks 0..nsteps as scf_step_keep_weights wrote them
+ * for the same starting state (without SCF_STEP_ACC_VALID); with them the
+ * recompute runs only the field passes, without w_hist it also recomputes the
+ * coefficients.  Blocks until the results are on the host. */
 scf_status scf_step_adjoint(scf_plan* plan, int64_t n, const void* x0, const void* y0,
                             const void* z0, const void* vx0, const void* vy0, const void* vz0,
                             const void* m, const scf_host* host, const double* centre0, double dt,
                             int32_t nsteps, void* const* lam, double* lam_centre,
-                            double* grad_host, void* ws, size_t ws_bytes, void* stream);
+                            double* grad_host, const void* w_hist, void* ws, size_t ws_bytes,
+                            void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): scf_step

@@ -2,11 +2,13 @@
 scf_step_adjoint with recomputation from checkpoints.
 
 The forward pass integrates nsteps leapfrog steps in segments of `checkpoint`
-steps, keeping only each segment's starting state (particles on the device,
-frame centre on the host).  The backward pass walks the segments in reverse;
-scf_step_adjoint recomputes a segment on the device from its checkpoint and
-returns the cotangents of its starting state, its starting centre and the
-host-potential parameters.  Differentiable inputs: the initial particle state,
+steps, keeping each segment's starting state (particles on the device, frame
+centre on the host) and the force weights of every kick (one row of
+(nmax + 1)(lmax + 1)^2 values per step, scf_step_keep_weights).  The backward
+pass walks the segments in reverse; scf_step_adjoint recomputes a segment's
+positions on the device from its checkpoint and the kept weights (no
+coefficient passes) and returns the cotangents of its starting state, its
+starting centre and the host-potential parameters.  Differentiable inputs: the initial particle state,
 the host parameters p[] of every component, and the initial centre (R0, V0).
 
 The stream-track loss of the adjoint workload (escapers' distance to a target
@@ -33,14 +35,19 @@ class SCFTrajectory(torch.autograd.Function):
             host = (list(zip(kinds, theta.detach().cpu().numpy().tolist())), G)
         st = [state0[i].detach().clone().contiguous() for i in range(6)]
         cen = centre0.detach().cpu().numpy().astype(np.float64)
+        wsz = plan.weights_size
+        # row j: the force weights of the kick at step j (a segment's first row
+        # is rewritten, with the same values, by the next segment's start-up)
+        hist = torch.empty((nsteps + 1) * wsz, dtype=st[0].dtype, device=st[0].device)
         segs = []
         done = 0
         while done < nsteps:
             k = min(checkpoint, nsteps - done)
-            segs.append((torch.stack([t.clone() for t in st]), cen.copy(), k))
-            cen, _ = plan.step(st, m, dt, k, host=host, centre=cen)
+            segs.append((torch.stack([t.clone() for t in st]), cen.copy(), k, done))
+            cen, _ = plan.step(st, m, dt, k, host=host, centre=cen, w_hist=hist[done * wsz:])
             done += k
         ctx.plan, ctx.m, ctx.host, ctx.dt, ctx.segs = plan, m, host, dt, segs
+        ctx.hist, ctx.wsz = hist, wsz
         ctx.ncomp = theta.shape[0]
         out = torch.stack(st)
         del n
@@ -55,10 +62,10 @@ class SCFTrajectory(torch.autograd.Function):
         lc = (g_centre.detach().cpu().numpy().astype(np.float64) if g_centre is not None
               else np.zeros(6))
         gtheta = np.zeros((ctx.ncomp, 3))
-        for st0, cen0, k in reversed(ctx.segs):
+        for st0, cen0, k, start in reversed(ctx.segs):
             st0l = [st0[i].contiguous() for i in range(6)]
             lc, gh = plan.step_adjoint(st0l, ctx.m, ctx.dt, k, lam, lc, host=ctx.host,
-                                       centre0=cen0)
+                                       centre0=cen0, w_hist=ctx.hist[start * ctx.wsz:])
             if gh.size:
                 gtheta += gh
         return (torch.stack(lam), torch.as_tensor(gtheta, dtype=torch.float64),

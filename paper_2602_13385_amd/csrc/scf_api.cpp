@@ -386,10 +386,16 @@ scf_status scf_forces(scf_plan* p, int64_t n, const void* x, const void* y, cons
                            pot, w + L.W, hp, cen, 0, 0.0, 0.0, s);
 }
 
-scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx, void* vy, void* vz,
-                    const void* m, void* ax, void* ay, void* az, uint32_t step_flags,
-                    const scf_host* host, double* centre, double dt, int32_t nsteps,
-                    double* coef_last, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// scf_step, and with w_hist non-null scf_step_keep_weights: the force
+// weights of the kick at x_k go to row k of w_hist instead of the workspace
+scf_status step_impl(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx, void* vy,
+                     void* vz, const void* m, void* ax, void* ay, void* az, uint32_t step_flags,
+                     const scf_host* host, double* centre, double dt, int32_t nsteps,
+                     double* coef_last, void* w_hist, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
   if (n < 0 || nsteps < 0) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nsteps >= 0");
   if (!std::isfinite(dt)) return fail(SCF_ERR_INVALID_ARG, "dt is not finite");
@@ -421,7 +427,9 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
     }
   };
   double* coef_int = (double*)(w + L.coef);
-  void* W = w + L.W;
+  const size_t wrow = (size_t)(p->nmaxc + 1) * (p->lmax + 1) * (p->lmax + 1) * p->rs;
+  // force weights of the kick at x_k
+  auto Wk = [&](int k) -> void* { return w_hist ? (char*)w_hist + (size_t)k * wrow : w + L.W; };
   const double h = 0.5 * dt;
   auto go = [&](auto tag) -> scf_status {
     using Rt = decltype(tag);
@@ -432,9 +440,11 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
     if (!(step_flags & SCF_STEP_ACC_VALID) || nsteps == 0) {
       // a(x0) from the particles themselves
       cen_row(row);
-      st = run_coeffs<Rt>(p, n, x, y, z, m, nsteps == 0 && coef_last ? coef_last : coef_int, W, w, L, s);
+      st = run_coeffs<Rt>(p, n, x, y, z, m, nsteps == 0 && coef_last ? coef_last : coef_int, Wk(0),
+                          w, L, s);
       if (st != SCF_OK) return st;
-      st = run_field<Rt>(p, n, x, y, z, vx, vy, vz, ax, ay, az, nullptr, W, hp, row, 0, 0.0, 0.0, s);
+      st = run_field<Rt>(p, n, x, y, z, vx, vy, vz, ax, ay, az, nullptr, Wk(0), hp, row, 0, 0.0,
+                         0.0, s);
       if (st != SCF_OK) return st;
     }
     if (nsteps == 0) return SCF_OK;
@@ -450,14 +460,15 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
     for (int k = 1; k <= nsteps; ++k) {
       const bool last = k == nsteps;
       cen_row(row);
-      st = run_coeffs<Rt>(p, n, x, y, z, m, last && coef_last ? coef_last : coef_int, W, w, L, s);
+      st = run_coeffs<Rt>(p, n, x, y, z, m, last && coef_last ? coef_last : coef_int, Wk(k), w, L,
+                          s);
       if (st != SCF_OK) return st;
       // closing half kick of step k merged with the opening half kick of
       // step k+1, then the drift of step k+1
       // (the accelerations are stored on the last step only: the merged
       // kicks of the other steps do not read them back)
       st = run_field<Rt>(p, n, x, y, z, vx, vy, vz, last ? ax : nullptr, last ? ay : nullptr,
-                         last ? az : nullptr, nullptr, W, hp, row, 1, last ? h : dt,
+                         last ? az : nullptr, nullptr, Wk(k), hp, row, 1, last ? h : dt,
                          last ? 0.0 : dt, s);
       if (st != SCF_OK) return st;
       centre_accel(hd, R, gc);
@@ -474,6 +485,32 @@ scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
     centre[3 + i] = V[i];
   }
   return SCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+scf_status scf_step(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx, void* vy, void* vz,
+                    const void* m, void* ax, void* ay, void* az, uint32_t step_flags,
+                    const scf_host* host, double* centre, double dt, int32_t nsteps,
+                    double* coef_last, void* ws, size_t ws_bytes, void* stream) {
+  return step_impl(p, n, x, y, z, vx, vy, vz, m, ax, ay, az, step_flags, host, centre, dt, nsteps,
+                   coef_last, nullptr, ws, ws_bytes, stream);
+}
+
+int64_t scf_plan_weights_size(const scf_plan* p) {
+  return p ? (int64_t)(p->nmaxc + 1) * (p->lmax + 1) * (p->lmax + 1) : 0;
+}
+
+scf_status scf_step_keep_weights(scf_plan* p, int64_t n, void* x, void* y, void* z, void* vx,
+                                 void* vy, void* vz, const void* m, void* ax, void* ay, void* az,
+                                 uint32_t step_flags, const scf_host* host, double* centre,
+                                 double dt, int32_t nsteps, double* coef_last, void* w_hist,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  if (n > 0 && !w_hist) return fail(SCF_ERR_INVALID_ARG, "w_hist is null");
+  return step_impl(p, n, x, y, z, vx, vy, vz, m, ax, ay, az, step_flags, host, centre, dt, nsteps,
+                   coef_last, n > 0 ? w_hist : nullptr, ws, ws_bytes, stream);
 }
 
 scf_status scf_step_batched(scf_plan* p, int32_t nclusters, const int64_t* offsets, void* x, void* y,
@@ -852,8 +889,8 @@ scf_status scf_adjoint_workspace_size(const scf_plan* p, int64_t n, int32_t nste
 scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* y0, const void* z0,
                             const void* vx0, const void* vy0, const void* vz0, const void* m,
                             const scf_host* host, const double* centre0, double dt, int32_t nsteps,
-                            void* const* lam, double* lam_centre, double* grad_host, void* ws,
-                            size_t ws_bytes, void* stream) {
+                            void* const* lam, double* lam_centre, double* grad_host,
+                            const void* w_hist, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return fail(SCF_ERR_INVALID_ARG, "plan is null");
   if (n < 0 || nsteps < 0) return fail(SCF_ERR_INVALID_ARG, "need n >= 0 and nsteps >= 0");
   if (!std::isfinite(dt)) return fail(SCF_ERR_INVALID_ARG, "dt is not finite");
@@ -907,7 +944,11 @@ scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* 
   };
   std::vector<double> S((size_t)(nsteps + 1) * 32, 0.0);
   auto Xk = [&](int k, int c) -> char* { return w + A.X + ((size_t)k * 3 + c) * n * rs; };
-  auto Wk = [&](int k) -> char* { return w + A.Wsv + (size_t)k * A.wsz * rs; };
+  // force weights of the kick at X_k: recorded by the forward pass, or
+  // recomputed here into the workspace
+  auto Wk = [&](int k) -> char* {
+    return w_hist ? (char*)w_hist + (size_t)k * A.wsz * rs : w + A.Wsv + (size_t)k * A.wsz * rs;
+  };
   char* Vb[3] = {w + A.V, w + A.V + n * rs, w + A.V + 2 * n * rs};
   char* Ab[3] = {w + A.A, w + A.A + n * rs, w + A.A + 2 * n * rs};
 
@@ -926,9 +967,11 @@ scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* 
         HIP_TRY(hipMemcpyAsync(Vb[c], src[3 + c], n * rs, hipMemcpyDeviceToDevice, s));
       }
       row_of(0, row);
-      st = run_coeffs<Rt>(p, n, Xk(0, 0), Xk(0, 1), Xk(0, 2), m, (double*)(w + A.L.coef), Wk(0), w,
-                          A.L, s);
-      if (st != SCF_OK) return st;
+      if (!w_hist) {
+        st = run_coeffs<Rt>(p, n, Xk(0, 0), Xk(0, 1), Xk(0, 2), m, (double*)(w + A.L.coef), Wk(0),
+                            w, A.L, s);
+        if (st != SCF_OK) return st;
+      }
       st = run_field<Rt>(p, n, Xk(0, 0), Xk(0, 1), Xk(0, 2), Vb[0], Vb[1], Vb[2], Ab[0], Ab[1],
                          Ab[2], nullptr, Wk(0), hp, row, 0, 0.0, 0.0, s);
       if (st != SCF_OK) return st;
@@ -937,9 +980,11 @@ scf_status scf_step_adjoint(scf_plan* p, int64_t n, const void* x0, const void* 
       HIP_TRY(launch_kick_drift(p->dtype, n, Xk(1, 0), Xk(1, 1), Xk(1, 2), Vb[0], Vb[1], Vb[2], Ab[0],
                                 Ab[1], Ab[2], h, dt, s));
       for (int k = 1; k <= nsteps; ++k) {
-        st = run_coeffs<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), m, (double*)(w + A.L.coef), Wk(k),
-                            w, A.L, s);
-        if (st != SCF_OK) return st;
+        if (!w_hist) {
+          st = run_coeffs<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), m, (double*)(w + A.L.coef),
+                              Wk(k), w, A.L, s);
+          if (st != SCF_OK) return st;
+        }
         if (k == nsteps) break;
         row_of(k, row);
         st = run_field<Rt>(p, n, Xk(k, 0), Xk(k, 1), Xk(k, 2), Vb[0], Vb[1], Vb[2], Ab[0], Ab[1],

@@ -127,6 +127,10 @@ SIGNATURES = {
     "scf_step": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                            C.c_uint32, C.POINTER(CHost), _dp, C.c_double, C.c_int32, _vp, _vp,
                            C.c_size_t, _vp]),
+    "scf_plan_weights_size": (C.c_int64, [_vp]),
+    "scf_step_keep_weights": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        _vp, _vp, C.c_uint32, C.POINTER(CHost), _dp, C.c_double,
+                                        C.c_int32, _vp, _vp, _vp, C.c_size_t, _vp]),
     "scf_noalloc_scratch_bytes": (C.c_size_t, []),
     "scf_step_noalloc": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    _vp, C.c_uint32, C.POINTER(CHost), _dp, C.c_double, C.c_int32,
@@ -136,7 +140,7 @@ SIGNATURES = {
                                    C.c_double, C.c_int32, _vp, _vp, C.c_size_t, _vp]),
     "scf_step_adjoint": (C.c_int, [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    C.POINTER(CHost), _dp, C.c_double, C.c_int32, C.POINTER(_vp),
-                                   _dp, _dp, _vp, C.c_size_t, _vp]),
+                                   _dp, _dp, _vp, _vp, C.c_size_t, _vp]),
     "scf_adjoint_workspace_size": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
     "scf_plan_num_variants": (C.c_int32, [_vp]),
     "scf_plan_variant": (C.c_int32, [_vp]),
@@ -401,10 +405,19 @@ class Plan:
                                 _ptr(ay), _ptr(az), _ptr(p), _ptr(ws), ws.numel(), _stream()))
         return (ax, ay, az, p) if pot else (ax, ay, az)
 
-    def step(self, st, m, dt, nsteps, host=None, centre=None, acc=None, coef_last=None):
+    @property
+    def weights_size(self):
+        """Elements of one force-weight row (see step's w_hist)."""
+        return int(lib().scf_plan_weights_size(self._h))
+
+    def step(self, st, m, dt, nsteps, host=None, centre=None, acc=None, coef_last=None,
+             w_hist=None):
         """Advance st = [x, y, z, vx, vy, vz] in place.  acc = [ax, ay, az]
         (in/out; pass the previous call's to skip the start-up evaluation).
-        Returns (centre (6,) numpy, acc)."""
+        w_hist (a contiguous device tensor of the plan's real type with at least
+        (nsteps + 1) * weights_size elements) keeps the force weights of every
+        kick for step_adjoint (scf_step_keep_weights).  Returns (centre (6,)
+        numpy, acc)."""
         torch = _torch()
         self._check_arrays(*st, m)
         n = st[0].numel()
@@ -414,11 +427,24 @@ class Plan:
         cen = (C.c_double * 6)(*[float(v) for v in (centre if centre is not None else np.zeros(6))])
         h = make_host(host[0], host[1]) if host is not None else None
         ws = self.workspace(n, device=st[0].device)
-        _check(lib().scf_step(self._h, n, *[_ptr(t) for t in st], _ptr(m), *[_ptr(t) for t in acc],
-                              STEP_ACC_VALID if acc_valid else 0,
-                              C.byref(h) if h is not None else None, C.cast(cen, _dp), float(dt),
-                              int(nsteps), _ptr(coef_last), _ptr(ws), ws.numel(), _stream()))
+        common = (STEP_ACC_VALID if acc_valid else 0, C.byref(h) if h is not None else None,
+                  C.cast(cen, _dp), float(dt), int(nsteps), _ptr(coef_last))
+        if w_hist is None:
+            _check(lib().scf_step(self._h, n, *[_ptr(t) for t in st], _ptr(m),
+                                  *[_ptr(t) for t in acc], *common, _ptr(ws), ws.numel(),
+                                  _stream()))
+        else:
+            self._check_weights(w_hist, nsteps, st[0])
+            _check(lib().scf_step_keep_weights(self._h, n, *[_ptr(t) for t in st], _ptr(m),
+                                               *[_ptr(t) for t in acc], *common, _ptr(w_hist),
+                                               _ptr(ws), ws.numel(), _stream()))
         return np.array(cen[:]), acc
+
+    def _check_weights(self, w_hist, nsteps, like):
+        if (w_hist.dtype != like.dtype or not w_hist.is_cuda or not w_hist.is_contiguous()
+                or w_hist.numel() < (int(nsteps) + 1) * self.weights_size):
+            raise TypeError("w_hist must be a contiguous CUDA tensor of the plan's real type "
+                            "with (nsteps + 1) * weights_size elements")
 
     def step_noalloc(self, st, m, dt, nsteps, host=None, centre=None, acc=None, coef_last=None):
         """step() through scf_step_noalloc: the library's static device scratch
@@ -446,13 +472,18 @@ class Plan:
                                    device=device or torch.device("cuda"))
         return self._ws
 
-    def step_adjoint(self, st0, m, dt, nsteps, lam, lam_centre, host=None, centre0=None):
+    def step_adjoint(self, st0, m, dt, nsteps, lam, lam_centre, host=None, centre0=None,
+                     w_hist=None):
         """Reverse mode of step() over nsteps steps starting from the synchronised
         state st0 = [x, y, z, vx, vy, vz] (not modified).  lam: 6 device tensors
         holding dL/d(final state), overwritten with dL/d(initial state).
-        lam_centre: (6,) dL/d(final R, V).  Returns (dL/d(initial R, V) (6,),
+        lam_centre: (6,) dL/d(final R, V).  w_hist: the force weights that
+        step(st0, ..., w_hist=) kept for this segment (then the recompute skips
+        the coefficient passes), or None.  Returns (dL/d(initial R, V) (6,),
         dL/d(host parameters) (ncomp, 3))."""
         self._check_arrays(*st0, m, *lam)
+        if w_hist is not None:
+            self._check_weights(w_hist, nsteps, st0[0])
         n = st0[0].numel()
         h = make_host(host[0], host[1]) if host is not None else None
         ncomp = h.ncomp if h is not None else 0
@@ -464,8 +495,8 @@ class Plan:
         _check(lib().scf_step_adjoint(self._h, n, *[_ptr(t) for t in st0], _ptr(m),
                                       C.byref(h) if h is not None else None, C.cast(cen, _dp),
                                       float(dt), int(nsteps), C.cast(lp, C.POINTER(C.c_void_p)),
-                                      C.cast(lc, _dp), C.cast(gh, _dp), _ptr(ws), ws.numel(),
-                                      _stream()))
+                                      C.cast(lc, _dp), C.cast(gh, _dp), _ptr(w_hist), _ptr(ws),
+                                      ws.numel(), _stream()))
         return np.array(lc[:]), np.array(gh[:3 * ncomp]).reshape(ncomp, 3)
 
     def power(self, coef):

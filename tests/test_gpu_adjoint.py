@@ -237,3 +237,47 @@ def test_track_loss_gradient_over_full_horizon(torch, S):
     rel = np.abs(g32 - g64) / np.abs(g64)
     print(f"  FP32 vs FP64 gradient, componentwise max {rel.max():.1e}", flush=True)
     assert (rel <= 1e-3).all(), rel
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_kept_weights_replay_equals_recompute(torch, S, dtype):
+    """scf_step_keep_weights advances the state exactly as scf_step does, and
+    scf_step_adjoint from the kept weights returns exactly what it returns when
+    it recomputes the coefficients (the same kernels on the same positions)."""
+    n, dt, nsteps = 3000, 0.005, 5
+    print(f"[kept weights] {dtype}", flush=True)
+    p = I.plummer(n, 5511)
+    st0 = _rounded(p.state(), dtype)
+    m = _dev(torch, _rounded(p.mass, dtype), dtype)
+    plan = S.Plan(10, 6, dtype=dtype)
+    host = (NFW, 1.0)
+    a = [_dev(torch, st0[i], dtype) for i in range(6)]
+    b = [_dev(torch, st0[i], dtype) for i in range(6)]
+    wsz = plan.weights_size
+    assert wsz == 11 * 49
+    hist = torch.full(((nsteps + 1) * wsz,), float("nan"), dtype=a[0].dtype, device="cuda")
+    ca, acc_a = plan.step(a, m, dt, nsteps, host=host, centre=CEN)
+    cb, acc_b = plan.step(b, m, dt, nsteps, host=host, centre=CEN, w_hist=hist)
+    torch.cuda.synchronize()
+    assert np.array_equal(ca, cb)
+    for u, v in zip(a + acc_a, b + acc_b):
+        assert torch.equal(u, v)
+    assert bool(torch.isfinite(hist).all())  # every kick's row, the start-up one included
+    # with the accelerations carried in, row 0 is left as it is
+    h2 = torch.full_like(hist, float("nan"))
+    plan.step(b, m, dt, nsteps, host=host, centre=cb, acc=acc_b, w_hist=h2)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(h2[:wsz]).all()) and bool(torch.isfinite(h2[wsz:]).all())
+
+    rng = np.random.default_rng(5512)
+    lam0 = _rounded(rng.normal(size=(6, n)), dtype)
+    lamc = rng.normal(size=6)
+    st = [_dev(torch, st0[i], dtype) for i in range(6)]
+    l1 = [_dev(torch, lam0[i], dtype) for i in range(6)]
+    l2 = [_dev(torch, lam0[i], dtype) for i in range(6)]
+    lc1, gh1 = plan.step_adjoint(st, m, dt, nsteps, l1, lamc, host=host, centre0=CEN)
+    lc2, gh2 = plan.step_adjoint(st, m, dt, nsteps, l2, lamc, host=host, centre0=CEN, w_hist=hist)
+    torch.cuda.synchronize()
+    assert np.array_equal(lc1, lc2) and np.array_equal(gh1, gh2)
+    for u, v in zip(l1, l2):
+        assert torch.equal(u, v)
