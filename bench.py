@@ -19,7 +19,7 @@ particles, 1e4 steps) in FP32 and FP64, the FP32 path's relative errors, the
 diagnostics and refresh-cadence legs, and the FP64 CPU oracle timed on a
 bounded sample.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the path runs on one GPU.
 """
 import argparse
 import hashlib
@@ -684,7 +684,7 @@ def main():
                     help="run a plain 1 GiB device copy (for counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs the hot path on one GPU only; --gpus {args.gpus} is not "
+        print(f"bench.py: the hot path runs on one GPU only; --gpus {args.gpus} is not "
               f"supported (the multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
     import torch
