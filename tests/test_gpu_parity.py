@@ -88,6 +88,8 @@ CASES = [  # (nmax, lmax, alpha, n, generator)
     (8, 3, 1.0, 3_001, "ball"),  # generic instance (runtime nmax < compiled bound)
     (20, 10, 1.0, 2_003, "hernquist"),  # generic instance at its compiled bound
     (12, 0, 1.0, 1_001, "plummer"),  # monopole only (generic, lmax 0)
+    (5, 1, 1.0, 1_003, "plummer"),  # lmax 1 and 2: split-degree parts left empty
+    (7, 2, 1.0, 1_009, "ball"),
     (9, 7, 1.0, 2_011, "ball"),  # generic instances of odd degree bounds
     (14, 9, 1.0, 2_017, "hernquist"),
     (6, 4, 0.5, 5_003, "plummer"),
